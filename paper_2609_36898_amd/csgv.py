@@ -1,0 +1,206 @@
+"""Python binding of libcsgv (ctypes; argument marshalling only).
+
+Every function here forwards to the C ABI of the same name in
+include/csgv.h; all decoding runs in the HIP kernels of libcsgv.so.  Device
+buffers are passed as torch tensors on a ROCm device (torch names HIP devices
+"cuda") or as raw integer addresses.  There is no CPU fallback: importing this
+module fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcsgv.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libcsgv.so is not built (run __graft_entry__.build() or python -m paper_2609_36898_amd._build)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+CSGV_OK, CSGV_EINVAL, CSGV_ECORRUPT, CSGV_ENOMEM, CSGV_EHIP = 0, -1, -2, -3, -4
+TASK_OK, TASK_INVALID, TASK_CORRUPT = 0, 1, 2
+MODE_PLAIN, MODE_PERSISTENT = 0, 2
+ALL_OPS = 63
+
+
+class VolumeInfo(ctypes.Structure):
+    _fields_ = [
+        ("dims", ctypes.c_uint32 * 3),
+        ("log2b", ctypes.c_uint32),
+        ("label_bytes", ctypes.c_uint32),
+        ("op_mask", ctypes.c_uint32),
+        ("n_bricks", ctypes.c_uint32),
+        ("grid", ctypes.c_uint32 * 3),
+        ("rans_freq", ctypes.c_uint16 * 16),
+        ("offsets_pos", ctypes.c_uint64),
+        ("dir_pos", ctypes.c_uint64),
+        ("total_bytes", ctypes.c_uint64),
+        ("neighbor_mode", ctypes.c_uint32),
+    ]
+
+
+class DecodeOpts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("wg_size", ctypes.c_int), ("wgs_per_cu", ctypes.c_int),
+                ("sort_tasks", ctypes.c_int)]
+
+
+class CsgvError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = _lib.csgv_last_error().decode(errors="replace")
+        super().__init__("%s failed (%d): %s" % (where, code, msg))
+        self.code = code
+
+
+_P, _U32, _U64, _I = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+_lib.csgv_last_error.restype = ctypes.c_char_p
+_lib.csgv_volume_parse.argtypes = [_P, _U64, ctypes.POINTER(VolumeInfo)]
+_lib.csgv_decode_bricks.argtypes = [_P, ctypes.POINTER(VolumeInfo), _P, _P, _P, _P, _U32, _P, _U64, _P,
+                                    ctypes.POINTER(DecodeOpts)]
+_lib.csgv_check_status.argtypes = [_P, _U32, _P]
+_lib.csgv_plan_create.argtypes = [ctypes.POINTER(VolumeInfo), _U32, ctypes.POINTER(DecodeOpts), ctypes.POINTER(_P)]
+_lib.csgv_plan_launch.argtypes = [_P, _P, _P, _P, _P, _P, _U32, _P, _U64, _P]
+_lib.csgv_plan_set_graph.argtypes = [_P, _I]
+_lib.csgv_plan_set_timing.argtypes = [_P, _I]
+_lib.csgv_plan_set_shape.argtypes = [_P, _I, _I]
+_lib.csgv_plan_get_opts.argtypes = [_P, ctypes.POINTER(DecodeOpts)]
+_lib.csgv_plan_last_kernel_ms.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
+_lib.csgv_plan_destroy.argtypes = [_P]
+_lib.csgv_encode_bricks.argtypes = [_P, _P, _U32, _U32, _P, _U32, _P, _P, _U32, _U32, _U32, _U32, _I,
+                                    ctypes.POINTER(_P), ctypes.POINTER(_U64)]
+_lib.csgv_free_host.argtypes = [_P]
+
+EXPORTED = [
+    "csgv_volume_parse", "csgv_decode_bricks", "csgv_check_status", "csgv_plan_create", "csgv_plan_launch",
+    "csgv_plan_set_graph", "csgv_plan_set_timing", "csgv_plan_set_shape", "csgv_plan_get_opts",
+    "csgv_plan_last_kernel_ms", "csgv_plan_destroy", "csgv_encode_bricks", "csgv_free_host", "csgv_last_error",
+]
+
+
+def _check(rc: int, where: str):
+    if rc != CSGV_OK:
+        raise CsgvError(rc, where)
+
+
+def _ptr(x) -> int | None:
+    """Device/host address of a torch tensor, numpy array or int (None -> NULL)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    raise TypeError("cannot take the address of %r" % type(x))
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def csgv_volume_parse(container) -> VolumeInfo:
+    """Header of a container held in host memory (bytes or uint8 numpy array)."""
+    buf = np.frombuffer(container, dtype=np.uint8) if isinstance(container, (bytes, bytearray)) else container
+    info = VolumeInfo()
+    _check(_lib.csgv_volume_parse(buf.ctypes.data, buf.nbytes, ctypes.byref(info)), "csgv_volume_parse")
+    return info
+
+
+def _opts(mode=None, wg_size=0, wgs_per_cu=0, sort_tasks=-1):
+    if mode is None:
+        return None
+    return DecodeOpts(mode, wg_size, wgs_per_cu, sort_tasks)
+
+
+def csgv_decode_bricks(stream, vol: VolumeInfo, d_container, d_brick_ids, d_lods, d_out_offsets, n: int, d_out,
+                       out_capacity: int, d_status=None, mode=None, wg_size=0, wgs_per_cu=0, sort_tasks=-1):
+    o = _opts(mode, wg_size, wgs_per_cu, sort_tasks)
+    rc = _lib.csgv_decode_bricks(_stream(stream), ctypes.byref(vol), _ptr(d_container), _ptr(d_brick_ids),
+                                 _ptr(d_lods), _ptr(d_out_offsets), n, _ptr(d_out), out_capacity, _ptr(d_status),
+                                 None if o is None else ctypes.byref(o))
+    _check(rc, "csgv_decode_bricks")
+
+
+def csgv_check_status(d_status, n: int, stream=None) -> bool:
+    rc = _lib.csgv_check_status(_ptr(d_status), n, _stream(stream))
+    if rc == CSGV_ECORRUPT:
+        return False
+    _check(rc, "csgv_check_status")
+    return True
+
+
+class csgv_plan:
+    """Owner of a csgv_plan* (csgv_plan_create / csgv_plan_destroy)."""
+
+    def __init__(self, vol: VolumeInfo, max_tasks: int, wg_size: int = 0, wgs_per_cu: int = 0, sort_tasks: int = -1):
+        self._vol = vol
+        self._h = ctypes.c_void_p()
+        o = DecodeOpts(MODE_PERSISTENT, wg_size, wgs_per_cu, sort_tasks)
+        _check(_lib.csgv_plan_create(ctypes.byref(vol), max_tasks, ctypes.byref(o), ctypes.byref(self._h)),
+               "csgv_plan_create")
+
+    def launch(self, stream, d_container, d_brick_ids, d_lods, d_out_offsets, n, d_out, out_capacity, d_status=None):
+        rc = _lib.csgv_plan_launch(self._h, _stream(stream), _ptr(d_container), _ptr(d_brick_ids), _ptr(d_lods),
+                                   _ptr(d_out_offsets), n, _ptr(d_out), out_capacity, _ptr(d_status))
+        _check(rc, "csgv_plan_launch")
+
+    def set_graph(self, enable: bool):
+        _check(_lib.csgv_plan_set_graph(self._h, int(enable)), "csgv_plan_set_graph")
+
+    def set_timing(self, enable: bool):
+        _check(_lib.csgv_plan_set_timing(self._h, int(enable)), "csgv_plan_set_timing")
+
+    def set_shape(self, wg_size: int, sort_tasks: bool):
+        _check(_lib.csgv_plan_set_shape(self._h, wg_size, int(sort_tasks)), "csgv_plan_set_shape")
+
+    def get_opts(self) -> DecodeOpts:
+        o = DecodeOpts()
+        _check(_lib.csgv_plan_get_opts(self._h, ctypes.byref(o)), "csgv_plan_get_opts")
+        return o
+
+    def last_kernel_ms(self) -> float:
+        v = ctypes.c_float()
+        _check(_lib.csgv_plan_last_kernel_ms(self._h, ctypes.byref(v)), "csgv_plan_last_kernel_ms")
+        return float(v.value)
+
+    def destroy(self):
+        if self._h:
+            _lib.csgv_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def csgv_encode_bricks(voxels: np.ndarray, log2b, label_bytes: int, dims=(0, 0, 0), default_log2b: int = 5,
+                       grid=None, origins=None, op_mask: int = ALL_OPS, neighbor_mode: int = 0,
+                       coder_policy: int = 0, lane_syms: int = 64, n_threads: int = 0) -> bytes:
+    """CPU encoder: concatenated bricks (brick k = (2^log2b[k])^3 labels, x fastest) -> container bytes."""
+    vox = np.ascontiguousarray(voxels, dtype=np.uint64 if label_bytes == 8 else np.uint32)
+    l2 = np.ascontiguousarray(np.asarray(log2b, dtype=np.uint8))
+    d = np.ascontiguousarray(np.asarray(dims, dtype=np.uint32))
+    g = None if grid is None else np.ascontiguousarray(np.asarray(grid, dtype=np.uint32))
+    org = None if origins is None else np.ascontiguousarray(np.asarray(origins, dtype=np.uint32).reshape(-1))
+    out = ctypes.c_void_p()
+    nbytes = ctypes.c_uint64()
+    rc = _lib.csgv_encode_bricks(vox.ctypes.data, l2.ctypes.data, len(l2), label_bytes, d.ctypes.data, default_log2b,
+                                 None if g is None else g.ctypes.data, None if org is None else org.ctypes.data,
+                                 op_mask, neighbor_mode, coder_policy, lane_syms, n_threads, ctypes.byref(out),
+                                 ctypes.byref(nbytes))
+    _check(rc, "csgv_encode_bricks")
+    try:
+        return ctypes.string_at(out.value, nbytes.value)
+    finally:
+        _lib.csgv_free_host(out)

@@ -1,0 +1,96 @@
+"""CPU checks of the C-ABI library: it loads, exports what include/csgv.h
+declares, rejects bad arguments before touching the GPU, and its host encoder
+writes the same bytes as the oracle's encoder."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    lib = os.path.join(ROOT, "paper_2609_36898_amd", "libcsgv.so")
+    if not os.path.exists(lib):
+        from paper_2609_36898_amd import _build
+        _build.build()
+    import paper_2609_36898_amd
+    return paper_2609_36898_amd
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "csgv.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(csgv_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol(P):
+    lib = os.path.join(ROOT, "paper_2609_36898_amd", "libcsgv.so")
+    out = subprocess.run(["nm", "-D", "--defined-only", lib], capture_output=True, text=True, check=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if l.strip())
+    declared = _declared()
+    assert declared, "no declarations found"
+    missing = [s for s in declared if s not in exported]
+    assert not missing, missing
+    assert set(P.csgv.EXPORTED) == set(declared)
+
+
+def test_volume_parse_rejects_bad_headers(P):
+    v = synth.voronoi_u32(64, 20, seed=1)
+    c = P.encode_volume(v, 5)
+    info = P.csgv_volume_parse(c)
+    assert info.n_bricks == 8 and info.label_bytes == 4 and list(info.grid) == [2, 2, 2]
+    bad = bytearray(c)
+    bad[0] ^= 1
+    with pytest.raises(P.CsgvError):
+        P.csgv_volume_parse(bytes(bad))
+    bad = bytearray(c)
+    bad[24] = 3  # label width 3
+    with pytest.raises(P.CsgvError):
+        P.csgv_volume_parse(bytes(bad))
+    with pytest.raises(P.CsgvError):
+        P.csgv_volume_parse(c[:100])
+
+
+def test_decode_rejects_null_arguments_synchronously(P):
+    c = P.encode_volume(synth.voronoi_u32(64, 20, seed=1), 5)
+    info = P.csgv_volume_parse(c)
+    with pytest.raises(P.CsgvError) as e:
+        P.csgv_decode_bricks(0, info, None, None, None, None, 4, None, 0, None)
+    assert e.value.code == P.csgv.CSGV_EINVAL
+    # n = 0 is a no-op
+    P.csgv_decode_bricks(0, info, None, None, None, None, 0, None, 0, None)
+
+
+@pytest.mark.parametrize("case", ["voronoi", "neurite", "uneven64", "masks"])
+def test_host_encoder_matches_oracle_encoder(P, case):
+    if case == "voronoi":
+        v = synth.voronoi_voids(128, 312, seed=2)
+        assert P.encode_volume(v, 5) == oracle.encode_volume(v, 5)
+    elif case == "neurite":
+        v = synth.neurite_u32(128, 200, seed=4)
+        for cp in (0, 1, 2):
+            assert P.encode_volume(v, 5, coder_policy=cp) == oracle.encode_volume(v, 5, coder=cp)
+    elif case == "uneven64":
+        bricks, l2 = [], []
+        for i in range(6):
+            b, kind = synth.uneven_brick_u64(64 if i % 2 else 32, 7, i)
+            bricks.append(b.reshape(-1))
+            l2.append(6 if i % 2 else 5)
+        flat = np.concatenate(bricks)
+        org = np.arange(18, dtype=np.uint32).reshape(6, 3)
+        a = P.csgv_encode_bricks(flat, l2, 8, origins=org)
+        b = oracle.encode_bricks(flat, l2, 8, origins=org)
+        assert a == b
+    else:
+        v = synth.voronoi_u32(64, 30, seed=5)
+        for mask in (0, 1, 7, 31, 63):
+            for nm in (0, 1):
+                assert P.encode_volume(v, 5, op_mask=mask, neighbor_mode=nm, lane_syms=8) == \
+                    oracle.encode_volume(v, 5, op_mask=mask, neighbor_mode=nm, lane_syms=8)
