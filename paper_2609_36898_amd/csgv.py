@@ -14,7 +14,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libcsgv.so")
+LIB_PATH = os.environ.get("CSGV_LIB_PATH") or os.path.join(_HERE, "libcsgv.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libcsgv.so is not built (run __graft_entry__.build() or python -m paper_2609_36898_amd._build)")

@@ -38,6 +38,11 @@
 #include "csgv_format.h"
 #include "decode_kernel.h"
 
+// Phase markers: empty unless a build defines CSGV_PHASE (timing probes).
+#ifndef CSGV_PHASE
+#define CSGV_PHASE(k) ((void)0)
+#endif
+
 namespace csgv {
 
 // ------------------------------------------------------------------ limits
@@ -397,6 +402,7 @@ __device__ void decode_levels(const SymSrc& src, Shared& sh, V* gOdd, V* gEven, 
             expected = 8 * total;
         }
         __syncthreads();
+        CSGV_PHASE(3 + 3 * i);
         // ------------------------------------------------ symbol chunks
         const uint32_t seg0 = i ? sh.sym_end[i - 1] : 0u, seg1 = sh.sym_end[i];
         uint32_t carry_state = 0, ops_done = 0, adv_done = sh.adv_total;
@@ -524,9 +530,11 @@ __device__ void decode_levels(const SymSrc& src, Shared& sh, V* gOdd, V* gEven, 
             sh.adv_total = adv_done;
         }
         __syncthreads();
+        CSGV_PHASE(4 + 3 * i);
         if (sh.err) return;
         resolve_level<NT, V>(cur, nodes, sh);
         __syncthreads();
+        CSGV_PHASE(5 + 3 * i);
         if (sh.err) return;
     }
     if (t == sh.L && sh.adv_total != sh.pc) {
@@ -614,11 +622,13 @@ __device__ void decode_task(const Params& P, Shared& sh, uint8_t* scratch) {
         rans_decode<NT>(P, sh, sh.sym_end[sh.t], symbuf);
     }
     __syncthreads();
+    CSGV_PHASE(2);
     if (!sh.err) {
         if (!sh.big) {
             decode_levels<NT, uint16_t>(src, sh, sh.gOdd, sh.gEven, sh.list);
             if (!sh.err) {
                 write_output<NT, uint16_t>(P, sh, (sh.t & 1) ? sh.gOdd : sh.gEven, false);
+                CSGV_PHASE(24);
                 return;
             }
         } else {
@@ -658,6 +668,7 @@ __global__ void __launch_bounds__(NT) decode_kernel(Params P) {
     uint32_t iter = 0;
     for (;;) {
         __syncthreads();
+        CSGV_PHASE(0);
         if (tid == 0) {
             uint32_t jt;
             if (P.queue) jt = atomicAdd(P.queue, 1u);
@@ -674,6 +685,7 @@ __global__ void __launch_bounds__(NT) decode_kernel(Params P) {
             }
         }
         __syncthreads();
+        CSGV_PHASE(1);
         ++iter;
         const uint32_t task = sh.task;
         if (task == 0xFFFFFFFFu) break;
