@@ -28,9 +28,10 @@
  *     range-ANS encoders), as static 16-symbol rANS (Duda 2013/2015) with
  *     W interleaved lanes (Giesen 2014).
  *
- * The byte layout and every reading of points the paper leaves open are the
- * "Format" section of the design notes; the comments below restate the rules
- * each routine follows.
+ * The paper gives the encoding only in outline, so the byte layout and the
+ * reading of every point it leaves open (node order, mode ties, stop bits,
+ * symbol codes, rANS parameters, error verdicts) are this codec's own; the
+ * comment above each routine states the rule it follows.
  */
 #include <stdint.h>
 #include <stdlib.h>

@@ -103,6 +103,16 @@ def test_rans_golden():
         assert rc == 0 and list(dec) == list(syms)
 
 
+def test_freq_table_golden():
+    for line in _lines("freq_tables.txt"):
+        counts, freq = [p.strip() for p in line.split("|")]
+        counts = [int(v) for v in counts.split()]
+        want = [int(v) for v in freq.split()]
+        got = [int(v) for v in oracle.make_freq(counts)]
+        assert got == want, (counts, got)
+        assert sum(got) in (0, 4096)
+
+
 # ----------------------------------------------------- mode / downsample
 def test_mode_rule_all_two_and_three_label_cubes():
     # every 2^3 brick over {0,1} and over {0,1,2}: LOD 1 = mode with ties to the smaller label
