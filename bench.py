@@ -1,21 +1,30 @@
-"""Benchmark: decoded GVoxel/s of the batched (persistent, graph-launched)
-CSGV brick decoder on one MI355X, with the plain one-launch-per-brick form,
-the decode kernel's HBM roofline fraction and the CPU oracle beside it.
+"""Benchmark of the CSGV brick decoder on one MI355X.
 
-Workload (the metric's reference configuration): a 512^3 u32 Voronoi label
-volume with 20,000 seeds and >= 10 % label-0 spherical voids, 32^3 bricks
-(4096 bricks), every brick decoded at full resolution in one batched launch.
-Inputs are resident in HBM before the timed region starts.
+Prints ONE JSON line.  The headline is the largest single-GPU batched
+workload: a 1024^3 u32 neurite volume (100,000 spline tubes), 32,768 bricks of
+32^3 at per-brick LOD uniform in {0..3}, decoded in one autotuned persistent
+launch (graph-captured plan).  Secondary entries: the 512^3 Voronoi volume with
+voids (4096 bricks, LOD 0), the 1024^3 u64 uneven batch (18,600 bricks of 32^3
+and 64^3, batched vs plain) and the 128^3 Voronoi volume (plain).
 
-Prints one JSON line.
+Every entry: decoded GVoxel/s over whole steps (inputs resident in HBM before
+the timed region), the decode kernel's HBM roofline fraction from HIP events
+on the plan's launch stream, bit-exactness of the timed output, and the CPU
+oracle (all host cores, and one thread on a sample) decoding the same tasks.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME ...] [--no-cpu] [--no-plain]
+    python bench.py --summarize-rocprof DIR --workload NAME   (profile summary text)
 """
 from __future__ import annotations
 
 import argparse
+import glob
 import hashlib
 import json
 import os
+import platform
 import re
+import subprocess
 import sys
 import time
 
@@ -25,13 +34,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+HEADLINE = "neurite1024"
+SECONDARY = ["voronoi512", "uneven1024", "voronoi128"]
+DECODE_KERNEL = "decode_kernel"
 
 
 def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def _kernel_source_hash() -> str:
+def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("decode_kernel.hip", "decode_kernel.h", "csgv_format.h"):
         with open(os.path.join(ROOT, "paper_2609_36898_amd", "csrc", f), "rb") as fh:
@@ -39,8 +51,8 @@ def _kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def _profiled_traffic(workload: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+def profiled_traffic(workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, when it
     was taken on the current kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", "decode_kernel_%s_traffic.txt" % workload)
     if not os.path.exists(path):
@@ -48,60 +60,115 @@ def _profiled_traffic(workload: str):
     txt = open(path).read()
     m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
     m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m_hash or not m_bytes or m_hash.group(1) != _kernel_source_hash():
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
         return None
     return float(m_bytes.group(1))
 
 
-def build_workload(seed: int = 0):
-    import synth
+def host_info():
+    model = platform.processor() or "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    sha = None
+    try:
+        sha = subprocess.run(["git", "-C", ROOT, "rev-parse", "--short=12", "HEAD"], capture_output=True,
+                             text=True, timeout=10).stdout.strip() or None
+    except Exception:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model, "git": sha}
+
+
+def cpu_threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+# ------------------------------------------------------------------ workloads
+class Workload:
+    """Container + task list of one workload (built with the product encoder)."""
+
+    def __init__(self, name, container, ids, lods, label_bytes, raw_lod0=None, config=None, plain=False):
+        self.name = name
+        self.container = container
+        self.ids = np.ascontiguousarray(ids, dtype=np.uint32)
+        self.lods = np.ascontiguousarray(lods, dtype=np.uint8)
+        self.label_bytes = label_bytes
+        self.raw_lod0 = raw_lod0  # expected output when every task is LOD 0 in brick order
+        self.config = config or {}
+        self.plain = plain
+
+
+def build_workload(name: str) -> Workload:
+    from synth import workloads as W
     import paper_2609_36898_amd as P
     t0 = time.time()
-    vol = synth.voronoi_voids(512, 20000, seed=seed, frac=0.10)
-    t1 = time.time()
-    container = P.encode_volume(vol, 5)
-    t2 = time.time()
-    _log("workload: generated %.1fs, encoded %.1fs, %d bytes (%.2f%% of raw)" %
-         (t1 - t0, t2 - t1, len(container), 100.0 * len(container) / vol.nbytes))
-    return vol, container
+    if name == "voronoi128":
+        vol = W.voronoi128()
+        c = P.encode_volume(vol, 5)
+        n = 64
+        wl = Workload(name, c, np.arange(n), np.zeros(n), 4, P.bricks_of_volume(vol, 5),
+                      {"workload": "voronoi128_u32_b32_lod0", "volume": [128] * 3, "bricks": n, "seeds": 500,
+                       "form": "plain"}, plain=True)
+    elif name == "voronoi512":
+        vol = W.voronoi512()
+        c = P.encode_volume(vol, 5)
+        n = 4096
+        wl = Workload(name, c, np.arange(n), np.zeros(n), 4, P.bricks_of_volume(vol, 5),
+                      {"workload": "voronoi512_voids_u32_b32_lod0", "volume": [512] * 3, "bricks": n,
+                       "seeds": 20000, "void_fraction_min": 0.10, "form": "persistent+graph"})
+    elif name == "neurite1024":
+        vol = W.neurite1024()
+        c = P.encode_volume(vol, 5)
+        del vol
+        n = 32768
+        wl = Workload(name, c, np.arange(n), W.neurite1024_lods(n), 4, None,
+                      {"workload": "neurite1024_u32_b32_lod0-3", "volume": [1024] * 3, "bricks": n,
+                       "tubes": 100000, "lod": "uniform 0..3 per brick", "form": "autotuned persistent+graph"})
+    elif name == "uneven1024":
+        flat, l2, origins, kinds = W.uneven1024()
+        c = P.csgv_encode_bricks(flat, l2, 8, dims=(1024, 1024, 1024), origins=origins)
+        n = len(l2)
+        wl = Workload(name, c, np.arange(n), np.zeros(n), 8, flat,
+                      {"workload": "uneven1024_u64_b32+b64_lod0", "volume": [1024] * 3, "bricks": n,
+                       "bricks_64": int((l2 == 6).sum()), "bricks_32": int((l2 == 5).sum()),
+                       "kinds": {"constant": int((kinds == 0).sum()), "voronoi": int((kinds == 1).sum()),
+                                 "noise": int((kinds == 2).sum())},
+                       "form": "persistent+graph vs plain"}, plain=True)
+    else:
+        raise ValueError("unknown workload " + name)
+    wl.config["compressed_bytes"] = len(c)
+    wl.config["label_bytes"] = wl.label_bytes
+    _log("%s: built in %.1f s, %d tasks, %d compressed bytes" % (name, time.time() - t0, len(wl.ids), len(c)))
+    return wl
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--plain-steps", type=int, default=2)
-    ap.add_argument("--wg", type=int, default=0, help="work-group size (0 = plan default)")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the decode path has no multi-GPU form in this build "
-              "(bricks are independent; sharding is by brick-id range, see the design notes)", file=sys.stderr)
-        sys.exit(2)
-
+# ---------------------------------------------------------------- measurement
+def measure(wl: Workload, args, dev):
     import torch
     import paper_2609_36898_amd as P
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-
-    vol, container = build_workload()
-    dv = P.DeviceVolume(container, device=dev)
-    n = dv.info.n_bricks
-    ids = np.arange(n, dtype=np.uint32)
-    lods = np.zeros(n, dtype=np.uint8)
-    d_ids, d_lods, d_offs, offs, total = dv.tasks(ids, lods, dev)
-    out = torch.empty(total, dtype=torch.int32, device=dev)
+    dv = P.DeviceVolume(wl.container, device=dev)
+    n = len(wl.ids)
+    d_ids, d_lods, d_offs, offs, total = dv.tasks(wl.ids, wl.lods, dev)
+    lb = wl.label_bytes
+    out = torch.empty(total, dtype=dv.dtype, device=dev)
     status = torch.full((n,), -1, dtype=torch.int32, device=dev)
     voxels = float(total)
-    offsets = np.frombuffer(container, dtype=np.uint64, count=n + 1, offset=int(dv.info.offsets_pos))
-    record_bytes = float(offsets[-1] - offsets[0])
-    alg_bytes = record_bytes + voxels * 4  # read every record once, write every label once
-
-    plan = P.csgv_plan(dv.info, n, wg_size=args.wg)
-    opts = plan.get_opts()
+    recs = np.frombuffer(wl.container, dtype=np.uint64, count=dv.info.n_bricks + 1, offset=int(dv.info.offsets_pos))
+    rec_bytes = float((recs[wl.ids.astype(np.int64) + 1] - recs[wl.ids.astype(np.int64)]).sum())
+    alg_bytes = rec_bytes + voxels * lb  # read each task's record once, write each label once
     stream = torch.cuda.current_stream(dev)
+    plan = P.csgv_plan(dv.info, n)
+    tune = None
+    if not args.no_tune:
+        rep = plan.autotune(stream, dv.tensor, d_ids, d_lods, d_offs, n, out, total, status,
+                            cache_path=args.tune_cache)
+        tune = {"from_cache": bool(rep.from_cache), "tried": int(rep.tried), "best_kernel_ms": round(rep.best_ms, 4),
+                "default_kernel_ms": round(rep.default_ms, 4)}
+    opts = plan.get_opts()
 
     def step():
         plan.launch(stream, dv.tensor, d_ids, d_lods, d_offs, n, out, total, status)
@@ -110,96 +177,212 @@ def main():
         step()
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     ev0.record(stream)
     for _ in range(args.steps):
         step()
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / args.steps
-    gvox = voxels / (ms * 1e-3) / 1e9
 
-    # bit-exactness of the timed output: LOD 0 of every brick is the raw brick
-    ref = torch.from_numpy(P.bricks_of_volume(vol, 5).view(np.int32)).to(dev)
-    bit_exact = bool(torch.equal(out, ref)) and bool((status == 0).all().item())
-    del ref
-
-    # dominant kernel: average decode-kernel duration from events on the launch stream
+    # the decode kernel alone: events on the plan's launch stream around it
     plan.set_timing(True)
     kms = []
-    for _ in range(max(3, args.steps // 2)):
+    for _ in range(max(3, args.steps)):
         step()
         kms.append(plan.last_kernel_ms())
     plan.set_timing(False)
     kernel_ms = float(np.mean(kms))
-    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
-    traffic = _profiled_traffic("voronoi512")
+    torch.cuda.synchronize()
 
-    # plain form: one kernel launch per brick
-    plain_out = torch.empty_like(out)
-    torch.cuda.synchronize()
-    p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    P.csgv_decode_bricks(stream, dv.info, dv.tensor, d_ids, d_lods, d_offs, n, plain_out, total, status,
-                         mode=P.MODE_PLAIN)
-    torch.cuda.synchronize()
-    p0.record(stream)
-    for _ in range(args.plain_steps):
+    st_ok = bool((status == 0).all().item())
+    bit_exact = None  # decided against the raw bricks (LOD 0) or the oracle below
+    if wl.raw_lod0 is not None:
+        ref = torch.from_numpy(wl.raw_lod0.view(np.int64 if lb == 8 else np.int32)).to(dev)
+        bit_exact = bool(torch.equal(out, ref)) and st_ok
+        del ref
+    kernel_gbs = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    res = {
+        "workload": wl.config.get("workload", wl.name), "tasks": n, "voxels": int(total),
+        "value": round(voxels / (ms * 1e-3) / 1e9, 3), "unit": "GVoxel/s", "ms_per_step": round(ms, 4),
+        "shape": {"wg_size": int(opts.wg_size), "lds_slots": int(opts.lds_slots),
+                  "wgs_per_cu": int(opts.wgs_per_cu), "sort_tasks": int(opts.sort_tasks)},
+        "autotune": tune,
+        "roofline": {"bound": "hbm", "achieved": round(kernel_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(kernel_gbs / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(wl.name),
+                     "kernel": DECODE_KERNEL, "kernel_ms": round(kernel_ms, 4), "alg_bytes_per_launch": alg_bytes,
+                     "label_bytes_per_launch": voxels * lb,
+                     "label_only_frac": round(voxels * lb / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "config": wl.config,
+    }
+
+    if args.calib_copy:
+        src = torch.empty(1 << 28, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    if wl.plain and not args.no_plain:
+        plain_out = torch.empty_like(out)
         P.csgv_decode_bricks(stream, dv.info, dv.tensor, d_ids, d_lods, d_offs, n, plain_out, total, status,
                              mode=P.MODE_PLAIN)
-    p1.record(stream)
-    torch.cuda.synchronize()
-    plain_ms = p0.elapsed_time(p1) / args.plain_steps
-    plain_exact = bool(torch.equal(plain_out, out))
-    del plain_out
+        torch.cuda.synchronize()
+        p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        p0.record(stream)
+        for _ in range(args.plain_steps):
+            P.csgv_decode_bricks(stream, dv.info, dv.tensor, d_ids, d_lods, d_offs, n, plain_out, total, status,
+                                 mode=P.MODE_PLAIN)
+        p1.record(stream)
+        torch.cuda.synchronize()
+        plain_ms = p0.elapsed_time(p1) / args.plain_steps
+        res["plain"] = {"value": round(voxels / (plain_ms * 1e-3) / 1e9, 3), "unit": "GVoxel/s",
+                        "ms_per_step": round(plain_ms, 3), "launches_per_step": n,
+                        "bit_exact": bool(torch.equal(plain_out, out))}
+        del plain_out
 
-    result = {
+    if not args.no_cpu:
+        got = out.cpu().numpy().view(np.uint64 if lb == 8 else np.uint32)
+        res["cpu_baseline"] = cpu_baseline(wl, offs, total, got)
+        if bit_exact is None:
+            bit_exact = res["cpu_baseline"]["matches_gpu"] and st_ok
+        del got
+    res["bit_exact"] = bit_exact
+    plan.destroy()
+    del out, status, dv
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(wl: Workload, offs, total, gpu_out):
+    """The oracle decoding the same task list: all host cores (16 at most) over
+    every task, and one thread over a bounded sample (about 2 s)."""
+    import oracle
+    lb = wl.label_bytes
+    threads = cpu_threads()
+    cpu_out = np.empty(total, dtype=np.uint64 if lb == 8 else np.uint32)
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        cpu_out, st = oracle.decode_tasks(wl.container, wl.ids, wl.lods, offs, total, lb, nthreads=threads,
+                                          out=cpu_out)
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
+    matches = bool(np.array_equal(cpu_out, gpu_out)) and bool((st == 0).all())
+    del cpu_out
+    n = len(wl.ids)
+    k = max(1, min(n, int(n * min(1.0, 2.0 / max(dt * threads, 1e-3)))))
+    sel = np.linspace(0, n - 1, k).astype(np.int64)
+    s_offs, s_total = _dense(wl, sel)
+    t0 = time.perf_counter()
+    oracle.decode_tasks(wl.container, wl.ids[sel], wl.lods[sel], s_offs, s_total, lb, nthreads=1)
+    dt1 = time.perf_counter() - t0
+    info = host_info()
+    return {"value": round(total / dt / 1e9, 4), "unit": "GVoxel/s", "cores": threads, "kind": "oracle",
+            "sample": "every task (%d), OpenMP over tasks on %d threads, median of 3 runs of %.2f s" %
+                      (n, threads, dt),
+            "single_thread": {"value": round(s_total / dt1 / 1e9, 4), "unit": "GVoxel/s",
+                              "sample": "%d of %d tasks evenly spaced, %.2f s" % (k, n, dt1)},
+            "nproc": info["nproc"], "cpu_model": info["cpu_model"], "matches_gpu": matches}
+
+
+def _dense(wl, sel):
+    import paper_2609_36898_amd as P
+    log2b = P.brick_log2b(wl.container)
+    return P.dense_offsets(log2b[wl.ids[sel].astype(np.int64)], wl.lods[sel])
+
+
+# ------------------------------------------------------------ profile summary
+def summarize_rocprof(directory: str, workload: str) -> str:
+    """Text summary of a rocprofv3 run of this script: kernel-trace statistics
+    and/or per-kernel counter means (FETCH_SIZE, WRITE_SIZE, ...)."""
+    import csv
+    lines = ["workload: %s" % workload, "kernel_source_sha256_16: %s" % kernel_source_hash()]
+    for path in sorted(glob.glob(os.path.join(directory, "**", "*kernel_stats.csv"), recursive=True)):
+        lines.append("# %s" % os.path.relpath(path, directory))
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                lines.append("%-60s calls %6s  avg_ns %12s  total_ns %14s  pct %s" % (
+                    row.get("Name", "")[:60], row.get("Calls"), row.get("AverageNs"), row.get("TotalDurationNs"),
+                    row.get("Percentage")))
+    for path in sorted(glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)):
+        sums = {}
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                name = row.get("Kernel_Name", "")
+                kind = "decode" if DECODE_KERNEL in name else name.split("(")[0][-48:]
+                sums.setdefault((kind, row.get("Counter_Name")), []).append(float(row.get("Counter_Value", 0) or 0))
+        lines.append("# %s" % os.path.relpath(path, directory))
+        for (kind, ctr), vals in sorted(sums.items()):
+            lines.append("%-50s %-18s dispatches %4d  mean %.6g  min %.6g  max %.6g" % (
+                kind, ctr, len(vals), float(np.mean(vals)), float(np.min(vals)), float(np.max(vals))))
+    return "\n".join(lines) + "\n"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--workload", nargs="*", default=None,
+                    help="workloads to run (first = headline); default: %s %s" % (HEADLINE, " ".join(SECONDARY)))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain one-launch-per-brick legs")
+    ap.add_argument("--no-tune", action="store_true", help="default launch shape instead of the autotuner")
+    ap.add_argument("--tune-cache", default=os.environ.get("CSGV_TUNE_CACHE", "/tmp/csgv_autotune.txt"))
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a 1 GiB device-to-device copy (reference kernel for HBM counter scaling)")
+    ap.add_argument("--summarize-rocprof", default=None, metavar="DIR")
+    args = ap.parse_args()
+    if args.summarize_rocprof:
+        sys.stdout.write(summarize_rocprof(args.summarize_rocprof, (args.workload or [HEADLINE])[0]))
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the decode path has no multi-GPU form in this build (bricks are "
+              "independent; a multi-GPU form would shard tasks by brick-id range with no exchange)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    names = args.workload if args.workload else [HEADLINE] + SECONDARY
+    results = []
+    for name in names:
+        wl = build_workload(name)
+        r = measure(wl, args, dev)
+        _log("%s: %.2f GVoxel/s, kernel %.3f ms, roofline %.3f, bit_exact %s" % (
+            name, r["value"], r["roofline"]["kernel_ms"], r["roofline"]["frac"], r["bit_exact"]))
+        results.append(r)
+        del wl
+    head = results[0]
+    line = {
         "metric": "decoded GVoxel/s (bit-exact), batched",
-        "value": round(gvox, 3) if bit_exact else None,
+        "value": head["value"] if head["bit_exact"] else None,
         "unit": "GVoxel/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32",
+        "dtype": "u64" if head["config"].get("label_bytes") == 8 else "u32",
         "data": "synthetic",
-        "config": {"workload": "voronoi512_voids_u32_b32_lod0", "volume": [512, 512, 512], "label_bytes": 4,
-                   "brick": 32, "bricks": n, "tasks": n, "lod": 0, "seeds": 20000, "void_fraction_min": 0.10,
-                   "form": "persistent+graph", "wg_size": int(opts.wg_size), "sort_tasks": int(opts.sort_tasks),
-                   "compressed_bytes": len(container)},
-        "bit_exact": bit_exact,
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "decode_kernel", "kernel_ms": round(kernel_ms, 4),
-                     "alg_bytes_per_launch": alg_bytes},
-        "plain": {"value": round(voxels / (plain_ms * 1e-3) / 1e9, 3), "unit": "GVoxel/s",
-                  "ms_per_step": round(plain_ms, 3), "launches_per_step": n, "bit_exact": plain_exact},
+        "config": head["config"],
+        "bit_exact": head["bit_exact"],
+        "roofline": head["roofline"],
+        "shape": head["shape"],
+        "autotune": head["autotune"],
     }
-
-    if not args.no_cpu:
-        import oracle
-        threads = min(16, os.cpu_count() or 1)
-        reps = 3
-        sel = np.arange(n, dtype=np.uint32)
-        times = []
-        cpu_out = np.empty(total, dtype=np.uint32)
-        for _ in range(reps):
-            t0 = time.perf_counter()
-            cpu_out, cpu_st = oracle.decode_tasks(container, sel, np.zeros(n, np.uint8), offs, total, 4,
-                                                  nthreads=threads, out=cpu_out)
-            times.append(time.perf_counter() - t0)
-        dt = float(np.median(times))
-        gpu_all = out.cpu().numpy().view(np.uint32)
-        result["cpu_baseline"] = {
-            "value": round(voxels / dt / 1e9, 4), "unit": "GVoxel/s", "cores": threads, "kind": "oracle",
-            "sample": "the whole task list (%d bricks, LOD 0), OpenMP over bricks, median of %d runs of %.2f s "
-                      "wall (%.1f thread-s each)" % (n, reps, dt, dt * threads),
-            "matches_gpu": bool(np.array_equal(cpu_out, gpu_all)) and bool((cpu_st == 0).all()),
-        }
-    plan.destroy()
-    print(json.dumps(result), flush=True)
+    if "cpu_baseline" in head:
+        line["cpu_baseline"] = head["cpu_baseline"]
+    if "plain" in head:
+        line["plain"] = head["plain"]
+    line["secondary"] = results[1:]
+    line["env"] = dict(host_info(), gpu=torch.cuda.get_device_name(dev), kernel_source=kernel_source_hash())
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -20,8 +20,8 @@
  *  - Argument errors are reported synchronously as CSGV_EINVAL before anything
  *    is enqueued; HIP failures as CSGV_EHIP.  csgv_last_error() describes the
  *    most recent failure of the calling thread.  No C++ exception crosses the ABI.
- *  - Per-task failures are reported in d_status (see csgv_task_status), never
- *    as a return code: a damaged record cannot fault or hang the decoder.
+ *  - Per-task failures are reported in d_status (see the CSGV_TASK_* words),
+ *    never as a return code: a damaged record cannot fault or hang the decoder.
  *
  * Volume container (little-endian; the byte-level format is this library's
  * own -- the paper describes the encoding only in outline):
@@ -33,7 +33,15 @@
  *   container start ("Brick Starts"; 64-bit, so no 16 GiB limit and no split
  *   buffers are needed); the last entry is the end of the final record.
  *   directory (optional): per brick u32 origin x, y, z and log2(brick side).
- *   brick records, each 8-byte aligned (layout in the design notes).
+ *   brick records, each 8-byte aligned:
+ *     u8 coder (0 plain 4-bit, 1 rANS), u8 log2(side), u8 label_bytes,
+ *     u8 log2(rANS lanes); u32 palette count; u32 sym_end[log2(side) + 1]
+ *     (symbols consumed after each level); rANS only: u32 word count of each
+ *     64-lane group, u32 state of each lane; the palette; the payload (plain:
+ *     two 4-bit symbols per byte, low nibble first; rANS: u16 words, group by
+ *     group).  A symbol is op | stop << 3 with op 0 PARENT, 1..3 NEIGHBOR_X/Y/Z,
+ *     4 PALETTE_ADV, 5 PALETTE_LAST, 6 PALETTE_DELTA (followed by its 4-bit
+ *     delta entries), 7 invalid.
  */
 #ifndef CSGV_H
 #define CSGV_H
@@ -61,9 +69,14 @@ enum {
     /* brick id >= n_bricks, LOD > log2(brick side), or the task's output range
        does not fit the output buffer: the output is left untouched */
     CSGV_TASK_INVALID = 1,
-    /* the brick record or its operation stream is malformed (any rule the
-       decoder checks, see the design notes): the task's output range is
-       zero-filled when it is valid, otherwise untouched */
+    /* the brick record or its operation stream is malformed: PARENT on the
+       root, a neighbour outside the brick, PALETTE_ADV past the palette,
+       PALETTE_LAST with no palette entry read yet, a delta of 0 or beyond the
+       entries read, operation 7, a level whose operations do not end exactly
+       at its sym_end, rANS words exhausted, or (at full resolution) a palette
+       count different from the PALETTE_ADV count; also a record whose offsets,
+       side, label width, coder or sizes do not fit.  The task's output range
+       is zero-filled when it is valid, otherwise left untouched */
     CSGV_TASK_CORRUPT = 2
 };
 
@@ -86,39 +99,54 @@ typedef struct {
     uint64_t dir_pos;      /* byte position of the brick directory, 0 if none */
     uint64_t total_bytes;  /* container size */
     uint32_t neighbor_mode;
+    uint32_t max_log2b;    /* largest log2(brick side) any record claims (sizes decoder scratch) */
 } csgv_volume_info;
 
+/* Launch shape.  Zero (or -1 for sort_tasks) selects the default. */
 typedef struct {
-    int mode;            /* CSGV_MODE_* (default PERSISTENT for plans, PLAIN for csgv_decode_bricks) */
-    int wg_size;         /* work-group size 256/512/1024; 0 = library default */
-    int wgs_per_cu;      /* persistent form: resident work-groups per compute unit; 0 = default */
-    int sort_tasks;      /* persistent form: pop tasks in decreasing estimated cost; -1 = default */
+    int mode;            /* CSGV_MODE_* (plans are always PERSISTENT)                      */
+    int wg_size;         /* work-group size 128, 256, 512 or 1024; default 256              */
+    int wgs_per_cu;      /* persistent form: work-groups per compute unit; default = as many
+                            as LDS and wave slots allow                                     */
+    int sort_tasks;      /* persistent form: pop tasks in decreasing estimated cost
+                            (record bytes + output bytes, by powers of two); default 1      */
+    int bricks_per_wave; /* tasks a wavefront takes at a time; only 1 is implemented        */
+    int lds_slots;       /* LDS split: 16-bit slots per work-group for the explicit nodes of
+                            levels 4 and 5 (bricks needing more use global scratch);
+                            default 10240, at most 32768                                   */
 } csgv_decode_opts;
 
 /*
- * Parse and validate a container header in host memory.
- * h_container: at least 128 bytes (bytes = available size).  Checks magic,
- * version, label width and that the offset table lies inside `bytes`.
- * Returns CSGV_OK or CSGV_EINVAL.
+ * Parse and validate a container held in host memory (the "Brick Starts"
+ * table and records of Methods > "Memory management").  `bytes` is the size
+ * of h_container and must cover the whole container (total_bytes): the
+ * offset table must lie inside it, and max_log2b is read from the records.
+ * Returns CSGV_OK or CSGV_EINVAL.  The device copy handed to the decode calls
+ * must hold the same total_bytes bytes.
  */
 csgv_status csgv_volume_parse(const void* h_container, uint64_t bytes, csgv_volume_info* out);
 
 /*
- * Decode a batch of bricks (the decode stage).
+ * Decode a batch of bricks: the decode stage of Methods > "GPU rendering
+ * pipeline" (bricks decoded in parallel into cache slots) at per-task LOD
+ * (Methods > "Memory management").
  *   vol            header of the container, from csgv_volume_parse.
  *   d_container    the whole container in device memory (vol->total_bytes).
  *   d_brick_ids    n tasks: brick id of each task.
  *   d_lods         n tasks: LOD, 0 = full resolution; LOD k yields a cube of
  *                  side (brick side >> k) whose voxels are the mode-of-8
  *                  multi-resolution labels of that level.
- *   d_out_offsets  n tasks: element offset of each task's output in d_out.
+ *   d_out_offsets  n tasks: element offset of each task's output in d_out, or
+ *                  NULL: tasks are packed back to back in task order (a task
+ *                  whose brick id, record or LOD is unusable occupies nothing).
  *   n              number of tasks (0 is allowed and enqueues nothing).
  *   d_out          labels of vol->label_bytes each; task j writes its cube,
- *                  linear with x fastest, at d_out + d_out_offsets[j].
+ *                  linear with x fastest, at d_out + offset of task j.
  *   out_capacity   number of label elements available in d_out.
  *   d_status       n task status words (CSGV_TASK_*), or NULL.
  *   opts           NULL for defaults (plain form).
- * Output ranges of different tasks must not overlap.  Returns CSGV_OK,
+ * Output ranges of different tasks must not overlap.  Device scratch is
+ * allocated and freed stream-ordered inside the call.  Returns CSGV_OK,
  * CSGV_EINVAL, CSGV_ENOMEM or CSGV_EHIP.
  */
 csgv_status csgv_decode_bricks(hipStream_t stream, const csgv_volume_info* vol, const void* d_container,
@@ -133,35 +161,40 @@ csgv_status csgv_decode_bricks(hipStream_t stream, const csgv_volume_info* vol, 
 csgv_status csgv_check_status(const uint32_t* d_status, uint32_t n, hipStream_t stream);
 
 /*
- * Batched plans: the persistent work-queue decoder with its scratch, an
- * optional cost-sorted task order and a captured HIP graph of the whole
- * launch sequence.  A plan serves one stream at a time; distinct plans may be
- * used from different threads.  max_tasks bounds n of every launch.
+ * Batched plans: the decode stage of Methods > "GPU rendering pipeline" as
+ * one persistent launch -- resident work-groups popping tasks from a device
+ * queue, optionally in decreasing estimated cost -- plus the rANS table and
+ * dense-offset kernels, all captured into one HIP graph.  The plan owns its
+ * device scratch (sized by vol->max_log2b and the grid).  A plan serves one
+ * stream at a time; distinct plans may be used from different threads.
+ * max_tasks bounds n of every launch.
  */
 typedef struct csgv_plan csgv_plan;
 
 csgv_status csgv_plan_create(const csgv_volume_info* vol, uint32_t max_tasks, const csgv_decode_opts* opts,
                              csgv_plan** out);
 
-/* Same task arguments as csgv_decode_bricks; enqueued on `stream`. */
+/* Same task arguments as csgv_decode_bricks (including NULL d_out_offsets);
+   enqueued on `stream`. */
 csgv_status csgv_plan_launch(csgv_plan* plan, hipStream_t stream, const void* d_container, const uint32_t* d_brick_ids,
                              const uint8_t* d_lods, const uint64_t* d_out_offsets, uint32_t n, void* d_out,
                              uint64_t out_capacity, uint32_t* d_status);
 
 /* Launch through a captured HIP graph of the whole sequence (default 1), or
    enqueue the kernels directly (0).  A graph is re-captured whenever the task
-   arguments differ from the previous launch. */
+   arguments or the shape differ from the previous launch. */
 csgv_status csgv_plan_set_graph(csgv_plan* plan, int enable);
 
 /* When enabled, launches bypass the graph and bracket the decode kernel with
    HIP events on the launch stream (read with csgv_plan_last_kernel_ms). */
 csgv_status csgv_plan_set_timing(csgv_plan* plan, int enable);
 
-/* Work-group size (256, 512 or 1024) and whether tasks are popped in
-   decreasing estimated cost (record bytes + output bytes, by powers of two). */
-csgv_status csgv_plan_set_shape(csgv_plan* plan, int wg_size, int sort_tasks);
+/* Change the launch shape (fields left 0, or -1 for sort_tasks and
+   wgs_per_cu, keep their value); scratch is re-sized when needed, which
+   synchronises the device. */
+csgv_status csgv_plan_set_opts(csgv_plan* plan, const csgv_decode_opts* opts);
 
-/* Options a plan resolved to (after autotuning or defaults). */
+/* The shape the plan launches with (wgs_per_cu resolved to the grid / CUs). */
 csgv_status csgv_plan_get_opts(const csgv_plan* plan, csgv_decode_opts* out);
 
 /* Duration of the most recent decode kernel launched by the plan, in milliseconds
@@ -171,7 +204,35 @@ csgv_status csgv_plan_last_kernel_ms(csgv_plan* plan, float* ms);
 void csgv_plan_destroy(csgv_plan* plan);
 
 /*
- * CPU encoder (host only, multi-threaded over bricks).
+ * Autotuner for the batched decode (the paper specialises its decoder per
+ * volume, Methods > "GPU rendering pipeline"; here the shape is searched at
+ * run time): times the plan on this task list under every candidate shape --
+ * work-group size {128, 256, 512} x LDS split {6144, 10240, 16384, 24576}
+ * slots, as many resident groups per CU as fit -- with HIP events on
+ * `stream` (first launch of each shape discarded, best of three kept), and
+ * leaves the plan on the fastest.  cache_path (or NULL): a text file of
+ * "key<TAB>wg lds wgs_per_cu" lines; the key is the GPU architecture, CU
+ * count, volume (label width, brick side, bricks, bytes) and task list (count,
+ * LOD histogram).  A key already in the file is applied without timing.
+ * Writes d_out/d_status like a launch; synchronises `stream`.
+ */
+typedef struct {
+    int from_cache;            /* 1: shape taken from cache_path */
+    int tried;                 /* shapes timed */
+    float best_ms;             /* decode-kernel time of the chosen shape */
+    float default_ms;          /* decode-kernel time of the default shape (256 threads, 10240 slots) */
+    csgv_decode_opts chosen;   /* the plan's shape afterwards */
+} csgv_tune_report;
+
+csgv_status csgv_plan_autotune(csgv_plan* plan, hipStream_t stream, const void* d_container,
+                               const uint32_t* d_brick_ids, const uint8_t* d_lods, const uint64_t* d_out_offsets,
+                               uint32_t n, void* d_out, uint64_t out_capacity, uint32_t* d_status,
+                               const char* cache_path, csgv_tune_report* report);
+
+/*
+ * CPU encoder (host only, multi-threaded over bricks; Methods > "Compressed
+ * segmentation volumes": one operation per explicit node, coarse to fine,
+ * copy from parent or neighbour when possible, else from the palette).
  *   h_voxels       all bricks concatenated; brick k holds (1 << h_log2b[k])^3
  *                  labels of label_bytes each, x fastest.
  *   h_log2b        per brick log2(side), 1..6.
@@ -191,6 +252,24 @@ csgv_status csgv_encode_bricks(const void* h_voxels, const uint8_t* h_log2b, uin
                                const uint32_t* h_origins, uint32_t op_mask, uint32_t neighbor_mode,
                                uint32_t coder_policy, uint32_t lane_syms, int n_threads, void** h_out,
                                uint64_t* out_bytes);
+
+/*
+ * Streaming form of the same encoder, for volumes produced piece by piece
+ * (e.g. in z-slabs): bricks are symbolised as they are added -- their voxels
+ * may be released right after csgv_encoder_add returns -- and the volume's
+ * rANS frequency table and records are built by csgv_encoder_finish, whose
+ * container is byte-identical to csgv_encode_bricks over all bricks in the
+ * order added.  with_directory: each csgv_encoder_add passes h_origins.
+ */
+typedef struct csgv_encoder csgv_encoder;
+
+csgv_status csgv_encoder_create(uint32_t label_bytes, const uint32_t dims[3], uint32_t default_log2b,
+                                const uint32_t grid[3], int with_directory, uint32_t op_mask, uint32_t neighbor_mode,
+                                uint32_t coder_policy, uint32_t lane_syms, int n_threads, csgv_encoder** out);
+csgv_status csgv_encoder_add(csgv_encoder* enc, const void* h_voxels, const uint8_t* h_log2b, uint32_t n_bricks,
+                             const uint32_t* h_origins);
+csgv_status csgv_encoder_finish(csgv_encoder* enc, void** h_out, uint64_t* out_bytes);
+void csgv_encoder_destroy(csgv_encoder* enc);
 
 void csgv_free_host(void* p);
 

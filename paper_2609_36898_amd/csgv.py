@@ -14,7 +14,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.environ.get("CSGV_LIB_PATH") or os.path.join(_HERE, "libcsgv.so")
+LIB_PATH = os.path.join(_HERE, "libcsgv.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libcsgv.so is not built (run __graft_entry__.build() or python -m paper_2609_36898_amd._build)")
@@ -40,12 +40,16 @@ class VolumeInfo(ctypes.Structure):
         ("dir_pos", ctypes.c_uint64),
         ("total_bytes", ctypes.c_uint64),
         ("neighbor_mode", ctypes.c_uint32),
+        ("max_log2b", ctypes.c_uint32),
     ]
 
 
 class DecodeOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("wg_size", ctypes.c_int), ("wgs_per_cu", ctypes.c_int),
-                ("sort_tasks", ctypes.c_int)]
+                ("sort_tasks", ctypes.c_int), ("bricks_per_wave", ctypes.c_int), ("lds_slots", ctypes.c_int)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 class CsgvError(RuntimeError):
@@ -65,18 +69,32 @@ _lib.csgv_plan_create.argtypes = [ctypes.POINTER(VolumeInfo), _U32, ctypes.POINT
 _lib.csgv_plan_launch.argtypes = [_P, _P, _P, _P, _P, _P, _U32, _P, _U64, _P]
 _lib.csgv_plan_set_graph.argtypes = [_P, _I]
 _lib.csgv_plan_set_timing.argtypes = [_P, _I]
-_lib.csgv_plan_set_shape.argtypes = [_P, _I, _I]
+_lib.csgv_plan_set_opts.argtypes = [_P, ctypes.POINTER(DecodeOpts)]
 _lib.csgv_plan_get_opts.argtypes = [_P, ctypes.POINTER(DecodeOpts)]
 _lib.csgv_plan_last_kernel_ms.argtypes = [_P, ctypes.POINTER(ctypes.c_float)]
 _lib.csgv_plan_destroy.argtypes = [_P]
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("from_cache", ctypes.c_int), ("tried", ctypes.c_int), ("best_ms", ctypes.c_float),
+                ("default_ms", ctypes.c_float), ("chosen", DecodeOpts)]
+
+
+_lib.csgv_plan_autotune.argtypes = [_P, _P, _P, _P, _P, _P, _U32, _P, _U64, _P, ctypes.c_char_p,
+                                    ctypes.POINTER(TuneReport)]
 _lib.csgv_encode_bricks.argtypes = [_P, _P, _U32, _U32, _P, _U32, _P, _P, _U32, _U32, _U32, _U32, _I,
                                     ctypes.POINTER(_P), ctypes.POINTER(_U64)]
 _lib.csgv_free_host.argtypes = [_P]
+_lib.csgv_encoder_create.argtypes = [_U32, _P, _U32, _P, _I, _U32, _U32, _U32, _U32, _I, ctypes.POINTER(_P)]
+_lib.csgv_encoder_add.argtypes = [_P, _P, _P, _U32, _P]
+_lib.csgv_encoder_finish.argtypes = [_P, ctypes.POINTER(_P), ctypes.POINTER(_U64)]
+_lib.csgv_encoder_destroy.argtypes = [_P]
 
 EXPORTED = [
     "csgv_volume_parse", "csgv_decode_bricks", "csgv_check_status", "csgv_plan_create", "csgv_plan_launch",
-    "csgv_plan_set_graph", "csgv_plan_set_timing", "csgv_plan_set_shape", "csgv_plan_get_opts",
-    "csgv_plan_last_kernel_ms", "csgv_plan_destroy", "csgv_encode_bricks", "csgv_free_host", "csgv_last_error",
+    "csgv_plan_set_graph", "csgv_plan_set_timing", "csgv_plan_set_opts", "csgv_plan_get_opts",
+    "csgv_plan_last_kernel_ms", "csgv_plan_destroy", "csgv_plan_autotune", "csgv_encode_bricks", "csgv_free_host", "csgv_last_error",
+    "csgv_encoder_create", "csgv_encoder_add", "csgv_encoder_finish", "csgv_encoder_destroy",
 ]
 
 
@@ -115,15 +133,16 @@ def csgv_volume_parse(container) -> VolumeInfo:
     return info
 
 
-def _opts(mode=None, wg_size=0, wgs_per_cu=0, sort_tasks=-1):
+def _opts(mode=None, wg_size=0, wgs_per_cu=0, sort_tasks=-1, bricks_per_wave=0, lds_slots=0):
     if mode is None:
         return None
-    return DecodeOpts(mode, wg_size, wgs_per_cu, sort_tasks)
+    return DecodeOpts(mode, wg_size, wgs_per_cu, sort_tasks, bricks_per_wave, lds_slots)
 
 
 def csgv_decode_bricks(stream, vol: VolumeInfo, d_container, d_brick_ids, d_lods, d_out_offsets, n: int, d_out,
-                       out_capacity: int, d_status=None, mode=None, wg_size=0, wgs_per_cu=0, sort_tasks=-1):
-    o = _opts(mode, wg_size, wgs_per_cu, sort_tasks)
+                       out_capacity: int, d_status=None, mode=None, wg_size=0, wgs_per_cu=0, sort_tasks=-1,
+                       bricks_per_wave=0, lds_slots=0):
+    o = _opts(mode, wg_size, wgs_per_cu, sort_tasks, bricks_per_wave, lds_slots)
     rc = _lib.csgv_decode_bricks(_stream(stream), ctypes.byref(vol), _ptr(d_container), _ptr(d_brick_ids),
                                  _ptr(d_lods), _ptr(d_out_offsets), n, _ptr(d_out), out_capacity, _ptr(d_status),
                                  None if o is None else ctypes.byref(o))
@@ -141,10 +160,11 @@ def csgv_check_status(d_status, n: int, stream=None) -> bool:
 class csgv_plan:
     """Owner of a csgv_plan* (csgv_plan_create / csgv_plan_destroy)."""
 
-    def __init__(self, vol: VolumeInfo, max_tasks: int, wg_size: int = 0, wgs_per_cu: int = 0, sort_tasks: int = -1):
+    def __init__(self, vol: VolumeInfo, max_tasks: int, wg_size: int = 0, wgs_per_cu: int = 0, sort_tasks: int = -1,
+                 bricks_per_wave: int = 0, lds_slots: int = 0):
         self._vol = vol
         self._h = ctypes.c_void_p()
-        o = DecodeOpts(MODE_PERSISTENT, wg_size, wgs_per_cu, sort_tasks)
+        o = DecodeOpts(MODE_PERSISTENT, wg_size, wgs_per_cu, sort_tasks, bricks_per_wave, lds_slots)
         _check(_lib.csgv_plan_create(ctypes.byref(vol), max_tasks, ctypes.byref(o), ctypes.byref(self._h)),
                "csgv_plan_create")
 
@@ -159,13 +179,24 @@ class csgv_plan:
     def set_timing(self, enable: bool):
         _check(_lib.csgv_plan_set_timing(self._h, int(enable)), "csgv_plan_set_timing")
 
-    def set_shape(self, wg_size: int, sort_tasks: bool):
-        _check(_lib.csgv_plan_set_shape(self._h, wg_size, int(sort_tasks)), "csgv_plan_set_shape")
+    def set_opts(self, wg_size: int = 0, wgs_per_cu: int = -1, sort_tasks: int = -1, bricks_per_wave: int = 0,
+                 lds_slots: int = 0):
+        o = DecodeOpts(MODE_PERSISTENT, wg_size, wgs_per_cu, sort_tasks, bricks_per_wave, lds_slots)
+        _check(_lib.csgv_plan_set_opts(self._h, ctypes.byref(o)), "csgv_plan_set_opts")
 
     def get_opts(self) -> DecodeOpts:
         o = DecodeOpts()
         _check(_lib.csgv_plan_get_opts(self._h, ctypes.byref(o)), "csgv_plan_get_opts")
         return o
+
+    def autotune(self, stream, d_container, d_brick_ids, d_lods, d_out_offsets, n, d_out, out_capacity,
+                 d_status=None, cache_path: str | None = None) -> TuneReport:
+        rep = TuneReport()
+        rc = _lib.csgv_plan_autotune(self._h, _stream(stream), _ptr(d_container), _ptr(d_brick_ids), _ptr(d_lods),
+                                     _ptr(d_out_offsets), n, _ptr(d_out), out_capacity, _ptr(d_status),
+                                     None if cache_path is None else cache_path.encode(), ctypes.byref(rep))
+        _check(rc, "csgv_plan_autotune")
+        return rep
 
     def last_kernel_ms(self) -> float:
         v = ctypes.c_float()
@@ -204,3 +235,46 @@ def csgv_encode_bricks(voxels: np.ndarray, log2b, label_bytes: int, dims=(0, 0, 
         return ctypes.string_at(out.value, nbytes.value)
     finally:
         _lib.csgv_free_host(out)
+
+
+class csgv_encoder:
+    """Streaming encoder (csgv_encoder_create / add / finish / destroy)."""
+
+    def __init__(self, label_bytes: int, dims=(0, 0, 0), default_log2b: int = 5, grid=None, with_directory=False,
+                 op_mask: int = ALL_OPS, neighbor_mode: int = 0, coder_policy: int = 0, lane_syms: int = 64,
+                 n_threads: int = 0):
+        self.label_bytes = label_bytes
+        self._dims = np.ascontiguousarray(np.asarray(dims, dtype=np.uint32))
+        self._grid = None if grid is None else np.ascontiguousarray(np.asarray(grid, dtype=np.uint32))
+        self._h = ctypes.c_void_p()
+        _check(_lib.csgv_encoder_create(label_bytes, self._dims.ctypes.data, default_log2b,
+                                        None if self._grid is None else self._grid.ctypes.data, int(with_directory),
+                                        op_mask, neighbor_mode, coder_policy, lane_syms, n_threads,
+                                        ctypes.byref(self._h)), "csgv_encoder_create")
+
+    def add(self, voxels: np.ndarray, log2b, origins=None):
+        vox = np.ascontiguousarray(voxels, dtype=np.uint64 if self.label_bytes == 8 else np.uint32)
+        l2 = np.ascontiguousarray(np.asarray(log2b, dtype=np.uint8))
+        org = None if origins is None else np.ascontiguousarray(np.asarray(origins, dtype=np.uint32).reshape(-1))
+        _check(_lib.csgv_encoder_add(self._h, vox.ctypes.data, l2.ctypes.data, len(l2),
+                                     None if org is None else org.ctypes.data), "csgv_encoder_add")
+
+    def finish(self) -> bytes:
+        out = ctypes.c_void_p()
+        nbytes = ctypes.c_uint64()
+        _check(_lib.csgv_encoder_finish(self._h, ctypes.byref(out), ctypes.byref(nbytes)), "csgv_encoder_finish")
+        try:
+            return ctypes.string_at(out.value, nbytes.value)
+        finally:
+            _lib.csgv_free_host(out)
+
+    def destroy(self):
+        if self._h:
+            _lib.csgv_encoder_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

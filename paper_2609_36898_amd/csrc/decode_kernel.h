@@ -8,13 +8,33 @@
 
 namespace csgv {
 
-// Per work-group scratch (global memory): decoded rANS symbols, then the
-// level grids and parent list of bricks decoded outside LDS.
-constexpr uint64_t kScratchSymBytes = ((8 * total_nodes(kMaxLog2b) + 64 + 255) / 256) * 256;
-constexpr uint64_t kBigOddSlots = 1u << 15;   // levels 1, 3, 5
-constexpr uint64_t kBigEvenSlots = 1u << 18;  // levels 0, 2, 4, 6
-constexpr uint64_t kBigListBytes = (1u << 15) * 2;
-constexpr uint64_t kScratchPerWG = kScratchSymBytes + 4 * (kBigOddSlots + kBigEvenSlots) + kBigListBytes;
+// ---- LDS of a decode work-group: a fixed part plus `cap16` 16-bit slots for
+// the explicit nodes of levels 4 and 5 (the LDS split chosen per launch).
+constexpr uint32_t kMaxWaves = 16;       // work-groups of up to 1024 threads
+constexpr uint32_t kFullSlots = 592;     // full grids of levels 0..3 at 0, 8, 16, 80
+constexpr uint32_t kEWords = 148;        // expansion bitmaps of levels 0..4: 1+1+2+16+128 words
+constexpr uint32_t kUBytes = 16384;      // rANS table | parent list + values | staged palette
+constexpr uint32_t kMaxCap16 = 32768;    // largest LDS slot share accepted
+constexpr uint32_t kDefaultCap16 = 10240;
+
+// ---- per work-group global scratch (byte offsets).  Big-path level storage
+// (32-bit slots), the level-5 bitmap used by 64^3 bricks, parent lists of
+// levels 6 (and every level on the big path), then the decoded rANS symbols
+// (4 bits each) whose size depends on the largest brick side of the volume.
+constexpr uint64_t kScrFull = 0;                                   // 592 x u32
+constexpr uint64_t kScrComp = 2560;                                // (4096 + 32768) x u32
+constexpr uint64_t kScrE5 = kScrComp + 4ull * (4096 + 32768);      // 1024 x u32
+constexpr uint64_t kScrWpre5 = kScrE5 + 4096;                      // 1024 x u16
+constexpr uint64_t kScrList = kScrWpre5 + 2048;                    // 32768 x u16
+constexpr uint64_t kScrPval = kScrList + 65536;                    // 32768 x u32
+constexpr uint64_t kScrSym = kScrPval + 131072;                    // 4-bit symbols
+constexpr uint64_t scratch_per_wg(uint32_t max_log2b) {
+    return kScrSym + ((4 * total_nodes(max_log2b) + 255) / 256) * 256;
+}
+
+struct RansFreq {
+    uint32_t w[8];  // 16 x u16 frequencies, two per word
+};
 
 struct Params {
     const uint8_t* vol;  // container in device memory
@@ -22,11 +42,13 @@ struct Params {
     uint64_t off_pos;
     uint32_t n_bricks;
     uint32_t label_bytes;
-    uint32_t freq_ok;
-    uint32_t freq[8];  // 16 x u16
+    uint32_t freq_ok;          // the volume's frequency table sums to 4096
+    uint32_t max_log2b;        // records with a larger brick side are rejected (scratch bound)
+    const uint32_t* rans_tab;  // decoding table built by rans_table_kernel (4096 entries)
     const uint32_t* ids;
     const uint8_t* lods;
-    const uint64_t* out_offs;
+    const uint64_t* out_offs;    // caller's element offsets, or null
+    const uint64_t* dense_offs;  // offsets computed on the device when out_offs is null
     uint32_t n_tasks;
     uint32_t task0;     // first task of a non-queue launch
     uint8_t* out;
@@ -36,12 +58,15 @@ struct Params {
     const uint32_t* order;  // optional pop order
     uint8_t* scratch;
     uint64_t scratch_stride;
+    uint32_t cap16;     // LDS slots for the explicit nodes of levels 4 and 5
 };
 
-size_t shared_bytes();
+size_t shared_bytes(uint32_t cap16);
 hipError_t set_kernel_attrs();
 hipError_t launch_decode(const Params& P, int wg_size, uint32_t grid, hipStream_t s);
 hipError_t launch_reset(uint32_t* q, hipStream_t s);
+hipError_t launch_rans_table(uint32_t* tab, const RansFreq& f, hipStream_t s);
 hipError_t launch_sort(const Params& P, uint32_t* cls, uint32_t* hist, uint32_t* order, hipStream_t s);
+hipError_t launch_dense_offsets(const Params& P, uint64_t* offs, hipStream_t s);
 
 }  // namespace csgv

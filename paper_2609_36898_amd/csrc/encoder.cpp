@@ -329,28 +329,71 @@ void parallel_for(uint32_t n, int threads, F&& fn) {
 
 }  // namespace
 
-extern "C" csgv_status csgv_encode_bricks(const void* h_voxels, const uint8_t* h_log2b, uint32_t n_bricks,
-                                          uint32_t label_bytes, const uint32_t dims[3], uint32_t default_log2b,
-                                          const uint32_t grid[3], const uint32_t* h_origins, uint32_t op_mask,
-                                          uint32_t neighbor_mode, uint32_t coder_policy, uint32_t lane_syms,
-                                          int n_threads, void** h_out, uint64_t* out_bytes) {
-    if (!h_out || !out_bytes || (n_bricks && (!h_voxels || !h_log2b))) return CSGV_EINVAL;
+// Streaming encoder: bricks are symbolised as they are added (the raw voxels
+// can be dropped right after), the volume's frequency table and the records
+// are produced once at the end.
+struct csgv_encoder {
+    uint32_t label_bytes = 4, default_log2b = 5, op_mask = 63, neighbor_mode = 0, coder_policy = 0, lane_syms = 64;
+    uint32_t dims[3] = {0, 0, 0}, grid[3] = {0, 0, 0};
+    bool has_grid = false, with_dir = false;
+    int threads = 1;
+    std::vector<BrickCode> bc;
+    std::vector<uint32_t> origins;  // 3 per brick when with_dir
+    std::vector<uint8_t> log2b;
+};
+
+extern "C" {
+
+csgv_status csgv_encoder_create(uint32_t label_bytes, const uint32_t dims[3], uint32_t default_log2b,
+                                const uint32_t grid[3], int with_directory, uint32_t op_mask, uint32_t neighbor_mode,
+                                uint32_t coder_policy, uint32_t lane_syms, int n_threads, csgv_encoder** out) {
+    if (!out) return CSGV_EINVAL;
     if (label_bytes != 4 && label_bytes != 8) return CSGV_EINVAL;
     if (coder_policy > 2) return CSGV_EINVAL;
-    if (lane_syms < 1) lane_syms = 1;
+    csgv_encoder* e = new csgv_encoder();
+    e->label_bytes = label_bytes;
+    e->default_log2b = default_log2b;
+    e->op_mask = op_mask;
+    e->neighbor_mode = neighbor_mode;
+    e->coder_policy = coder_policy;
+    e->lane_syms = lane_syms < 1 ? 1 : lane_syms;
+    for (int a = 0; a < 3; ++a) {
+        e->dims[a] = dims ? dims[a] : 0;
+        e->grid[a] = grid ? grid[a] : 0;
+    }
+    e->with_dir = with_directory != 0;
+    e->threads = n_threads > 0 ? n_threads : (int)std::max(1u, std::thread::hardware_concurrency());
+    *out = e;
+    return CSGV_OK;
+}
+
+csgv_status csgv_encoder_add(csgv_encoder* e, const void* h_voxels, const uint8_t* h_log2b, uint32_t n_bricks,
+                             const uint32_t* h_origins) {
+    if (!e || (n_bricks && (!h_voxels || !h_log2b))) return CSGV_EINVAL;
+    if (e->with_dir && n_bricks && !h_origins) return CSGV_EINVAL;
     std::vector<size_t> vox_off(n_bricks + 1, 0);
     for (uint32_t k = 0; k < n_bricks; ++k) {
         if (h_log2b[k] < 1 || h_log2b[k] > kMaxLog2b) return CSGV_EINVAL;
         vox_off[k + 1] = vox_off[k] + (size_t(1) << (3 * h_log2b[k]));
     }
-    int threads = n_threads > 0 ? n_threads : (int)std::max(1u, std::thread::hardware_concurrency());
-    std::vector<BrickCode> bc(n_bricks);
-    std::vector<Worker> workers(threads);
+    const size_t base = e->bc.size();
+    e->bc.resize(base + n_bricks);
+    std::vector<Worker> workers(e->threads);
     const uint8_t* vox = (const uint8_t*)h_voxels;
-    parallel_for(n_bricks, threads, [&](uint32_t k, int t) {
-        encode_brick(vox + vox_off[k] * label_bytes, label_bytes, h_log2b[k], op_mask, neighbor_mode, workers[t], bc[k]);
+    const uint32_t lb = e->label_bytes;
+    parallel_for(n_bricks, e->threads, [&](uint32_t k, int t) {
+        encode_brick(vox + vox_off[k] * lb, lb, h_log2b[k], e->op_mask, e->neighbor_mode, workers[t], e->bc[base + k]);
     });
-    workers.clear();
+    e->log2b.insert(e->log2b.end(), h_log2b, h_log2b + n_bricks);
+    if (e->with_dir) e->origins.insert(e->origins.end(), h_origins, h_origins + 3ull * n_bricks);
+    return CSGV_OK;
+}
+
+csgv_status csgv_encoder_finish(csgv_encoder* e, void** h_out, uint64_t* out_bytes) {
+    if (!e || !h_out || !out_bytes) return CSGV_EINVAL;
+    const uint32_t n_bricks = (uint32_t)e->bc.size();
+    const uint32_t label_bytes = e->label_bytes, lane_syms = e->lane_syms, coder_policy = e->coder_policy;
+    std::vector<BrickCode>& bc = e->bc;
     uint64_t cnt[16] = {0};
     for (auto& c : bc)
         for (uint8_t s : c.sym) ++cnt[s];
@@ -359,7 +402,7 @@ extern "C" csgv_status csgv_encode_bricks(const void* h_voxels, const uint8_t* h
     uint32_t cum[17];
     cum[0] = 0;
     for (int s = 0; s < 16; ++s) cum[s + 1] = cum[s] + freq[s];
-    parallel_for(n_bricks, threads, [&](uint32_t k, int) {
+    parallel_for(n_bricks, e->threads, [&](uint32_t k, int) {
         std::vector<uint8_t> raw, rans;
         if (coder_policy != 2) build_record(bc[k], label_bytes, false, lane_syms, freq, cum, raw);
         if (coder_policy != 1) build_record(bc[k], label_bytes, true, lane_syms, freq, cum, rans);
@@ -370,9 +413,10 @@ extern "C" csgv_status csgv_encode_bricks(const void* h_voxels, const uint8_t* h
         std::vector<uint8_t>().swap(bc[k].sym);
         std::vector<uint64_t>().swap(bc[k].pal);
     });
+    const bool dir = e->with_dir;
     const uint64_t off_pos = kHeaderBytes;
-    const uint64_t dir_pos = h_origins ? (off_pos + 8ull * (n_bricks + 1) + 7) / 8 * 8 : 0;
-    uint64_t rec0 = h_origins ? dir_pos + 16ull * n_bricks : off_pos + 8ull * (n_bricks + 1);
+    const uint64_t dir_pos = dir ? (off_pos + 8ull * (n_bricks + 1) + 7) / 8 * 8 : 0;
+    uint64_t rec0 = dir ? dir_pos + 16ull * n_bricks : off_pos + 8ull * (n_bricks + 1);
     rec0 = (rec0 + 7) / 8 * 8;
     uint64_t total = rec0;
     for (auto& c : bc) total += c.rec.size();
@@ -383,34 +427,56 @@ extern "C" csgv_status csgv_encode_bricks(const void* h_voxels, const uint8_t* h
     w32(0, kMagic);
     w32(4, kVersion);
     for (int a = 0; a < 3; ++a) {
-        w32(kHdrDims + 4 * a, dims ? dims[a] : 0);
-        w32(kHdrGrid + 4 * a, grid ? grid[a] : 0);
+        w32(kHdrDims + 4 * a, e->dims[a]);
+        w32(kHdrGrid + 4 * a, e->grid[a]);
     }
-    w32(kHdrLog2b, default_log2b);
+    w32(kHdrLog2b, e->default_log2b);
     w32(kHdrLabelBytes, label_bytes);
-    w32(kHdrOpMask, op_mask);
+    w32(kHdrOpMask, e->op_mask);
     w32(kHdrNBricks, n_bricks);
     memcpy(buf + kHdrFreq, freq, 32);
     w64(kHdrOffsetsPos, off_pos);
     w64(kHdrDirPos, dir_pos);
     w64(kHdrTotal, total);
-    w32(kHdrNeighborMode, neighbor_mode);
+    w32(kHdrNeighborMode, e->neighbor_mode);
     uint64_t pos = rec0;
     for (uint32_t k = 0; k < n_bricks; ++k) {
         w64(off_pos + 8ull * k, pos);
-        if (h_origins) {
-            for (int a = 0; a < 3; ++a) w32(dir_pos + 16ull * k + 4 * a, h_origins[3 * k + a]);
-            w32(dir_pos + 16ull * k + 12, h_log2b[k]);
+        if (dir) {
+            for (int a = 0; a < 3; ++a) w32(dir_pos + 16ull * k + 4 * a, e->origins[3ull * k + a]);
+            w32(dir_pos + 16ull * k + 12, e->log2b[k]);
         }
         pos += bc[k].rec.size();
     }
     w64(off_pos + 8ull * n_bricks, pos);
-    parallel_for(n_bricks, threads, [&](uint32_t k, int) {
+    parallel_for(n_bricks, e->threads, [&](uint32_t k, int) {
         uint64_t at;
         memcpy(&at, buf + off_pos + 8ull * k, 8);
         memcpy(buf + at, bc[k].rec.data(), bc[k].rec.size());
+        std::vector<uint8_t>().swap(bc[k].rec);
     });
+    bc.clear();
     *h_out = buf;
     *out_bytes = total;
     return CSGV_OK;
 }
+
+void csgv_encoder_destroy(csgv_encoder* e) { delete e; }
+
+csgv_status csgv_encode_bricks(const void* h_voxels, const uint8_t* h_log2b, uint32_t n_bricks, uint32_t label_bytes,
+                               const uint32_t dims[3], uint32_t default_log2b, const uint32_t grid[3],
+                               const uint32_t* h_origins, uint32_t op_mask, uint32_t neighbor_mode,
+                               uint32_t coder_policy, uint32_t lane_syms, int n_threads, void** h_out,
+                               uint64_t* out_bytes) {
+    if (!h_out || !out_bytes || (n_bricks && (!h_voxels || !h_log2b))) return CSGV_EINVAL;
+    csgv_encoder* e = nullptr;
+    csgv_status st = csgv_encoder_create(label_bytes, dims, default_log2b, grid, h_origins != nullptr, op_mask,
+                                         neighbor_mode, coder_policy, lane_syms, n_threads, &e);
+    if (st != CSGV_OK) return st;
+    st = csgv_encoder_add(e, h_voxels, h_log2b, n_bricks, h_origins);
+    if (st == CSGV_OK) st = csgv_encoder_finish(e, h_out, out_bytes);
+    csgv_encoder_destroy(e);
+    return st;
+}
+
+}  // extern "C"

@@ -49,6 +49,7 @@ def _load():
     lib.synth_uneven_brick_u64.argtypes = [P, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64]
     lib.synth_uneven_tile_split.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
     lib.synth_test_brick_u64.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64]
+    lib.synth_uneven_batch_u64.argtypes = [P, P, P, ctypes.c_uint64, ctypes.c_uint64, P, ctypes.c_int]
     lib.synth_pcg32_first.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
     lib.synth_pcg32_first.restype = ctypes.c_uint32
     _lib = lib
@@ -93,6 +94,22 @@ def uneven_brick_u64(b: int, seed: int, brick_id: int) -> tuple[np.ndarray, int]
     out = np.empty((b, b, b), dtype=np.uint64)
     kind = _load().synth_uneven_brick_u64(out.ctypes.data, b, seed, brick_id)
     return out, int(kind)
+
+
+def uneven_batch_u64(log2b, seed: int = 0):
+    """Bricks 0..n-1 of the uneven batch concatenated (brick k = uneven_brick_u64(2^log2b[k], seed, k)).
+
+    Returns (flat u64 labels, element offset of each brick, kinds)."""
+    l2 = np.ascontiguousarray(np.asarray(log2b, dtype=np.uint8))
+    sizes = np.left_shift(np.uint64(1), 3 * l2.astype(np.uint64))
+    offs = np.zeros(len(l2), dtype=np.uint64)
+    if len(l2) > 1:
+        offs[1:] = np.cumsum(sizes)[:-1]
+    flat = np.empty(int(sizes.sum()), dtype=np.uint64)
+    kinds = np.zeros(len(l2), dtype=np.int32)
+    _load().synth_uneven_batch_u64(flat.ctypes.data, offs.ctypes.data, l2.ctypes.data, len(l2), seed,
+                                   kinds.ctypes.data, _threads())
+    return flat, offs, kinds
 
 
 def uneven_tile_split(seed: int, tile: int) -> bool:

@@ -542,3 +542,17 @@ void synth_test_brick_u64(uint64_t* out, int b, int kind, int nlab, uint64_t bas
                 }
     }
 }
+
+/* ------------------------------------------------- uneven batch (parallel) */
+/*
+ * Bricks 0..n-1 of the uneven-content batch into one flat array: brick k is
+ * synth_uneven_brick_u64(seed, k) of side 1 << log2b[k], stored from element
+ * elem_off[k].  kinds[k] receives its kind.  Same bytes as brick-by-brick
+ * generation; OpenMP over bricks.
+ */
+void synth_uneven_batch_u64(uint64_t* out, const uint64_t* elem_off, const uint8_t* log2b, uint64_t n, uint64_t seed,
+                            int32_t* kinds, int nthreads) {
+#pragma omp parallel for schedule(dynamic, 8) num_threads(nthreads > 0 ? nthreads : 1)
+    for (long k = 0; k < (long)n; k++)
+        kinds[k] = synth_uneven_brick_u64(out + elem_off[k], 1 << log2b[k], seed, (uint64_t)k);
+}

@@ -94,3 +94,48 @@ def test_host_encoder_matches_oracle_encoder(P, case):
             for nm in (0, 1):
                 assert P.encode_volume(v, 5, op_mask=mask, neighbor_mode=nm, lane_syms=8) == \
                     oracle.encode_volume(v, 5, op_mask=mask, neighbor_mode=nm, lane_syms=8)
+
+
+def test_volume_parse_bounds_by_given_bytes(P):
+    c = P.encode_volume(synth.voronoi_u32(64, 20, seed=1), 5)
+    info = P.csgv_volume_parse(c)
+    assert info.total_bytes == len(c) and info.max_log2b == 5
+    # truncated container: header claims more bytes than were given
+    with pytest.raises(P.CsgvError) as e:
+        P.csgv_volume_parse(c[:-8])
+    assert e.value.code == P.csgv.CSGV_EINVAL
+    # inflated total_bytes in the header
+    bad = bytearray(c)
+    bad[96:104] = np.uint64(len(c) + 4096).tobytes()
+    with pytest.raises(P.CsgvError):
+        P.csgv_volume_parse(bytes(bad))
+    # offset table running past the container
+    bad = bytearray(c)
+    bad[32:36] = np.uint32(1 << 20).tobytes()
+    with pytest.raises(P.CsgvError):
+        P.csgv_volume_parse(bytes(bad))
+
+
+def test_volume_parse_max_brick_side_from_records(P):
+    bricks, l2 = [], []
+    for i in range(4):
+        b, _ = synth.uneven_brick_u64(64 if i == 2 else 32, 3, i)
+        bricks.append(b.reshape(-1))
+        l2.append(6 if i == 2 else 5)
+    c = P.csgv_encode_bricks(np.concatenate(bricks), l2, 8, origins=np.zeros((4, 3), np.uint32))
+    assert P.csgv_volume_parse(c).max_log2b == 6
+    c = P.encode_volume(synth.voronoi_u32(32, 9, seed=2), 4)
+    assert P.csgv_volume_parse(c).max_log2b == 4
+
+
+def test_streaming_encoder_matches_one_shot(P):
+    v = synth.voronoi_voids(128, 312, seed=2)
+    flat = P.bricks_of_volume(v, 5)
+    whole = P.encode_volume(v, 5)
+    enc = P.csgv.csgv_encoder(4, dims=(128, 128, 128), default_log2b=5, grid=(4, 4, 4))
+    per = 32 ** 3
+    for k0 in range(0, 64, 24):  # three uneven slabs of bricks
+        k1 = min(64, k0 + 24)
+        enc.add(flat[k0 * per:k1 * per], [5] * (k1 - k0))
+    assert enc.finish() == whole
+    enc.destroy()

@@ -111,7 +111,8 @@ def _random_stream_container(seed, n, lb, Ls=(1, 2, 3, 4, 5), coder_mix=True):
     for k, (L, syms, se, pal) in enumerate(infos):
         coder = (k % 2) if coder_mix else 0
         recs.append(streams.record_bytes(L, lb, syms, se, pal, coder=coder, freq=freq, log2W=k % 9))
-    return streams.container(recs, lb, freq=freq), [i[0] for i in infos]
+    # the header's brick side must cover every record: output offsets are sized from it
+    return streams.container(recs, lb, freq=freq, log2b=max(Ls)), [i[0] for i in infos]
 
 
 @pytest.mark.parametrize("lb", [4, 8])
@@ -122,6 +123,15 @@ def test_random_valid_streams(P, lb):
         for lod in range(L + 1):
             ids.append(k)
             lods.append(lod)
+    _compare(P, c, ids, lods)
+
+
+@pytest.mark.parametrize("lb", [4, 8])
+def test_random_valid_streams_64_bricks(P, lb):
+    # 64^3 bricks: the level-6 grids, long neighbour chains and delta chains of a random grammar walk
+    c, Ls = _random_stream_container(30 + lb, 3, lb, Ls=(6,))
+    ids = [k for k in range(3) for lod in range(7)]
+    lods = [lod for k in range(3) for lod in range(7)]
     _compare(P, c, ids, lods)
 
 
