@@ -112,8 +112,8 @@ typedef struct {
                             (record bytes + output bytes, by powers of two); default 1      */
     int bricks_per_wave; /* tasks a wavefront takes at a time; only 1 is implemented        */
     int lds_slots;       /* LDS split: 16-bit slots per work-group for the explicit nodes of
-                            levels 4 and 5 (bricks needing more use global scratch);
-                            default 10240, at most 32768                                   */
+                            level 5 (bricks needing more use global scratch); the area also
+                            holds the rANS table, so 8192..32760; default 10240             */
 } csgv_decode_opts;
 
 /*
@@ -207,7 +207,7 @@ void csgv_plan_destroy(csgv_plan* plan);
  * Autotuner for the batched decode (the paper specialises its decoder per
  * volume, Methods > "GPU rendering pipeline"; here the shape is searched at
  * run time): times the plan on this task list under every candidate shape --
- * work-group size {128, 256, 512} x LDS split {6144, 10240, 16384, 24576}
+ * work-group size {128, 256, 512} x LDS split {8192, 10240, 16384, 24576}
  * slots, as many resident groups per CU as fit -- with HIP events on
  * `stream` (first launch of each shape discarded, best of three kept), and
  * leaves the plan on the fastest.  cache_path (or NULL): a text file of
@@ -228,6 +228,81 @@ csgv_status csgv_plan_autotune(csgv_plan* plan, hipStream_t stream, const void* 
                                const uint32_t* d_brick_ids, const uint8_t* d_lods, const uint64_t* d_out_offsets,
                                uint32_t n, void* d_out, uint64_t out_capacity, uint32_t* d_status,
                                const char* cache_path, csgv_tune_report* report);
+
+/*
+ * Served decode: the request / provision / assign stages of Methods > "GPU
+ * rendering pipeline" on the host in front of batched decode plans, with the
+ * brick cache of Methods > "Memory management" in caller device memory.
+ *  - A request is a set of (brick id, LOD) pairs that must all be resident in
+ *    the cache; it completes when the last missing pair has been decoded.
+ *  - The cache (d_cache, cache_elements labels of vol->label_bytes) is carved
+ *    into slots of one cube each (side = brick side >> LOD; a slot keeps its
+ *    size once carved).  Residency is keyed by (id, LOD); pairs of pending
+ *    requests are pinned, unpinned resident pairs are evicted least recently
+ *    used first within their size class, and a full cache with nothing pinned
+ *    is reset (defragmentation).
+ *  - Admission is in arrival order and waits for cache space.  Admitted misses
+ *    are decoded in batches of up to max_batch tasks on n_streams HIP streams:
+ *    whenever a stream is free, the queued tasks go out on it, so requests
+ *    admitted while earlier batches run overlap with them on the device.
+ *  - Times are seconds on the server's steady clock (csgv_server_clock).
+ *  - A completed request's pairs stay pinned (their cache contents cannot
+ *    change) until the next csgv_server_step, or with keep_pinned until
+ *    csgv_server_release.
+ * h_brick_log2b: side exponent per brick (n_bricks entries), or NULL for
+ * vol->log2b everywhere.  One server is driven by one host thread.
+ */
+typedef struct csgv_server csgv_server;
+
+typedef struct {
+    int n_streams;            /* HIP streams (batches in flight), default 2, at most 16 */
+    uint32_t max_batch;       /* tasks per batch, default 4096 */
+    int keep_pinned;          /* completed requests stay pinned until csgv_server_release */
+    csgv_decode_opts shape;   /* launch shape of every batch (fields 0 / -1 = defaults) */
+} csgv_server_config;
+
+typedef struct {
+    uint64_t req;             /* id returned by csgv_server_submit (or run order) */
+    double t_arrival, t_admit, t_done;  /* seconds; latency = t_done - t_arrival */
+    uint32_t n_pairs;         /* distinct pairs of the request */
+    uint32_t n_decoded;       /* pairs this request caused to be decoded (cache misses) */
+    int32_t status;           /* 0 ok, -1 rejected: the request does not fit the whole cache */
+} csgv_request_done;
+
+typedef struct {
+    /* pairs_requested = hits (resident) + joined (already queued or in flight) + decoded */
+    uint64_t requests_done, pairs_requested, hits, joined, decoded, evictions, resets, batches;
+    uint64_t decoded_elements, requested_elements, cache_top, resident, pinned, failed_tasks;
+    uint32_t max_batch_seen;
+} csgv_server_stats;
+
+csgv_status csgv_server_create(const csgv_volume_info* vol, const void* d_container, const uint8_t* h_brick_log2b,
+                               void* d_cache, uint64_t cache_elements, const csgv_server_config* cfg,
+                               csgv_server** out);
+/* Seconds since the server was created (the time base of every request). */
+double csgv_server_clock(const csgv_server* server);
+/* Queue a request arriving at t_arrival (it is not admitted before then).
+   EINVAL when a pair names no brick or a LOD beyond its brick side. */
+csgv_status csgv_server_submit(csgv_server* server, const uint32_t* h_ids, const uint8_t* h_lods, uint32_t n,
+                               double t_arrival, uint64_t* req);
+/* One scheduling step now: retire finished batches, admit, launch.
+   *busy = 1 while requests are waiting or batches are queued or in flight. */
+csgv_status csgv_server_step(csgv_server* server, int* busy);
+/* Completed requests (up to cap) since the last drain. */
+csgv_status csgv_server_drain(csgv_server* server, csgv_request_done* out, uint32_t cap, uint32_t* n_out);
+csgv_status csgv_server_release(csgv_server* server, uint64_t req);
+/* Element offset in d_cache of a resident pair (EINVAL if not resident). */
+csgv_status csgv_server_where(csgv_server* server, uint32_t id, uint8_t lod, uint64_t* elem_offset);
+/* Serve a whole trace: request r is pairs [h_req_start[r], h_req_start[r+1])
+   arriving h_arrival[r] seconds after the call starts; steps until every
+   request has completed; out[r] is request r's record (times relative to
+   the call's start). */
+csgv_status csgv_server_run(csgv_server* server, const uint32_t* h_ids, const uint8_t* h_lods,
+                            const uint64_t* h_req_start, uint32_t n_req, const double* h_arrival,
+                            csgv_request_done* out);
+csgv_status csgv_server_get_stats(csgv_server* server, csgv_server_stats* out);
+const char* csgv_server_last_error(void);
+void csgv_server_destroy(csgv_server* server);
 
 /*
  * CPU encoder (host only, multi-threaded over bricks; Methods > "Compressed

@@ -278,3 +278,132 @@ class csgv_encoder:
             self.destroy()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ serving
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("n_streams", ctypes.c_int), ("max_batch", ctypes.c_uint32), ("keep_pinned", ctypes.c_int),
+                ("shape", DecodeOpts)]
+
+
+class RequestDone(ctypes.Structure):
+    _fields_ = [("req", ctypes.c_uint64), ("t_arrival", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("n_pairs", ctypes.c_uint32), ("n_decoded", ctypes.c_uint32),
+                ("status", ctypes.c_int32)]
+
+
+# numpy view of csgv_request_done (48 bytes: 4 bytes of tail padding)
+REQUEST_DONE_DTYPE = np.dtype([("req", "<u8"), ("t_arrival", "<f8"), ("t_admit", "<f8"), ("t_done", "<f8"),
+                               ("n_pairs", "<u4"), ("n_decoded", "<u4"), ("status", "<i4"), ("_pad", "<i4")])
+assert REQUEST_DONE_DTYPE.itemsize == ctypes.sizeof(RequestDone)
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("requests_done", "pairs_requested", "hits", "joined", "decoded",
+                                               "evictions", "resets", "batches", "decoded_elements",
+                                               "requested_elements", "cache_top", "resident", "pinned",
+                                               "failed_tasks")] + [("max_batch_seen", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+_lib.csgv_server_create.argtypes = [ctypes.POINTER(VolumeInfo), _P, _P, _P, _U64, ctypes.POINTER(ServerConfig),
+                                    ctypes.POINTER(_P)]
+_lib.csgv_server_clock.argtypes = [_P]
+_lib.csgv_server_clock.restype = ctypes.c_double
+_lib.csgv_server_submit.argtypes = [_P, _P, _P, _U32, ctypes.c_double, ctypes.POINTER(_U64)]
+_lib.csgv_server_step.argtypes = [_P, ctypes.POINTER(_I)]
+_lib.csgv_server_drain.argtypes = [_P, ctypes.POINTER(RequestDone), _U32, ctypes.POINTER(_U32)]
+_lib.csgv_server_release.argtypes = [_P, _U64]
+_lib.csgv_server_where.argtypes = [_P, _U32, ctypes.c_uint8, ctypes.POINTER(_U64)]
+_lib.csgv_server_run.argtypes = [_P, _P, _P, _P, _U32, _P, ctypes.POINTER(RequestDone)]
+_lib.csgv_server_get_stats.argtypes = [_P, ctypes.POINTER(ServerStats)]
+_lib.csgv_server_last_error.restype = ctypes.c_char_p
+_lib.csgv_server_destroy.argtypes = [_P]
+EXPORTED += ["csgv_server_create", "csgv_server_clock", "csgv_server_submit", "csgv_server_step", "csgv_server_drain",
+             "csgv_server_release", "csgv_server_where", "csgv_server_run", "csgv_server_get_stats",
+             "csgv_server_last_error", "csgv_server_destroy"]
+
+
+def _scheck(rc: int, where: str):
+    if rc != CSGV_OK:
+        msg = _lib.csgv_server_last_error().decode(errors="replace")
+        err = CsgvError(rc, where)
+        err.args = ("%s failed (%d): %s" % (where, rc, msg),)
+        raise err
+
+
+class csgv_server:
+    """Owner of a csgv_server* (served decode with a brick cache in d_cache)."""
+
+    def __init__(self, vol: VolumeInfo, d_container, d_cache, cache_elements: int, brick_log2b=None,
+                 n_streams: int = 2, max_batch: int = 4096, keep_pinned: bool = False, wg_size: int = 0,
+                 lds_slots: int = 0, sort_tasks: int = -1):
+        self._h = ctypes.c_void_p()
+        self._l2 = None if brick_log2b is None else np.ascontiguousarray(np.asarray(brick_log2b, dtype=np.uint8))
+        cfg = ServerConfig(n_streams, max_batch, int(keep_pinned),
+                           DecodeOpts(MODE_PERSISTENT, wg_size, 0, sort_tasks, 0, lds_slots))
+        _scheck(_lib.csgv_server_create(ctypes.byref(vol), _ptr(d_container),
+                                        None if self._l2 is None else self._l2.ctypes.data, _ptr(d_cache),
+                                        cache_elements, ctypes.byref(cfg), ctypes.byref(self._h)),
+                "csgv_server_create")
+
+    def clock(self) -> float:
+        return float(_lib.csgv_server_clock(self._h))
+
+    def submit(self, ids, lods, t_arrival: float) -> int:
+        ids = np.ascontiguousarray(np.asarray(ids, dtype=np.uint32))
+        lods = np.ascontiguousarray(np.asarray(lods, dtype=np.uint8))
+        req = ctypes.c_uint64()
+        _scheck(_lib.csgv_server_submit(self._h, ids.ctypes.data, lods.ctypes.data, len(ids), t_arrival,
+                                        ctypes.byref(req)), "csgv_server_submit")
+        return int(req.value)
+
+    def step(self) -> bool:
+        busy = ctypes.c_int()
+        _scheck(_lib.csgv_server_step(self._h, ctypes.byref(busy)), "csgv_server_step")
+        return bool(busy.value)
+
+    def drain(self, cap: int = 4096):
+        buf = (RequestDone * cap)()
+        n = ctypes.c_uint32()
+        _scheck(_lib.csgv_server_drain(self._h, buf, cap, ctypes.byref(n)), "csgv_server_drain")
+        return [buf[i] for i in range(n.value)]
+
+    def release(self, req: int):
+        _scheck(_lib.csgv_server_release(self._h, req), "csgv_server_release")
+
+    def where(self, brick_id: int, lod: int) -> int:
+        off = ctypes.c_uint64()
+        _scheck(_lib.csgv_server_where(self._h, brick_id, lod, ctypes.byref(off)), "csgv_server_where")
+        return int(off.value)
+
+    def run(self, ids, lods, starts, arrivals):
+        """Serve a whole trace; returns a structured array of per-request records."""
+        ids = np.ascontiguousarray(np.asarray(ids, dtype=np.uint32))
+        lods = np.ascontiguousarray(np.asarray(lods, dtype=np.uint8))
+        starts = np.ascontiguousarray(np.asarray(starts, dtype=np.uint64))
+        arrivals = np.ascontiguousarray(np.asarray(arrivals, dtype=np.float64))
+        n = len(starts) - 1
+        rec = np.zeros(max(n, 1), dtype=REQUEST_DONE_DTYPE)
+        out = ctypes.cast(rec.ctypes.data, ctypes.POINTER(RequestDone))
+        _scheck(_lib.csgv_server_run(self._h, ids.ctypes.data, lods.ctypes.data, starts.ctypes.data, n,
+                                     arrivals.ctypes.data, out), "csgv_server_run")
+        return rec[:n]
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _scheck(_lib.csgv_server_get_stats(self._h, ctypes.byref(s)), "csgv_server_get_stats")
+        return s.as_dict()
+
+    def destroy(self):
+        if self._h:
+            _lib.csgv_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -73,11 +73,10 @@ int device_lds_per_cu() {
 
 bool valid_wg(int wg) { return wg == 128 || wg == 256 || wg == 512 || wg == 1024; }
 
-// resident work-groups per CU for a shape: LDS bound, wave bound (32 waves per CU)
+// resident work-groups per CU for a shape (HIP occupancy: registers, LDS, waves)
 int resident_per_cu(int wg, uint32_t cap16) {
     const int by_lds = device_lds_per_cu() / (int)shared_bytes(cap16);
-    const int by_waves = 32 / (wg / 64);
-    return std::max(1, std::min(by_lds, by_waves));
+    return std::max(1, std::min(by_lds, max_resident_per_cu(wg, std::max<uint32_t>(cap16, kMinCap16))));
 }
 
 RansFreq pack_freq(const csgv_volume_info* vol, bool* ok) {
@@ -129,7 +128,10 @@ csgv_status check_opts(const csgv_decode_opts* o) {
     if (!o) return CSGV_OK;
     if (o->wg_size != 0 && !valid_wg(o->wg_size)) return fail(CSGV_EINVAL, "wg_size %d (128, 256, 512 or 1024)", o->wg_size);
     if (o->lds_slots < 0 || (uint32_t)o->lds_slots > kMaxCap16)
-        return fail(CSGV_EINVAL, "lds_slots %d (0..%u)", o->lds_slots, kMaxCap16);
+        return fail(CSGV_EINVAL, "lds_slots %d (0, or %u..%u)", o->lds_slots, kMinCap16, kMaxCap16);
+    if (o->lds_slots > 0 && (uint32_t)o->lds_slots < kMinCap16)
+        return fail(CSGV_EINVAL, "lds_slots %d below %u (the slot area also holds the rANS table)", o->lds_slots,
+                    kMinCap16);
     if (o->bricks_per_wave < 0) return fail(CSGV_EINVAL, "bricks_per_wave %d", o->bricks_per_wave);
     if (o->wgs_per_cu < -1) return fail(CSGV_EINVAL, "wgs_per_cu %d", o->wgs_per_cu);
     return CSGV_OK;
@@ -144,6 +146,7 @@ struct Bufs {
     uint32_t* order = nullptr;  // max_tasks
     uint32_t* rans_tab = nullptr;
     uint64_t* dense = nullptr;  // max_tasks
+    bool table_built = false;   // rans_tab already holds the volume's table
 };
 
 uint64_t aux_bytes(uint32_t max_tasks) {
@@ -173,7 +176,7 @@ hipError_t enqueue_persistent(Params P, const Bufs& b, const csgv_volume_info* v
     if (e != hipSuccess) return e;
     bool ok;
     const RansFreq f = pack_freq(vol, &ok);
-    if (ok && (e = launch_rans_table(b.rans_tab, f, s)) != hipSuccess) return e;
+    if (ok && !b.table_built && (e = launch_rans_table(b.rans_tab, f, s)) != hipSuccess) return e;
     if (!P.out_offs) {
         P.dense_offs = b.dense;
         if ((e = launch_dense_offsets(P, b.dense, s)) != hipSuccess) return e;
@@ -247,7 +250,7 @@ csgv_status csgv_decode_bricks(hipStream_t stream, const csgv_volume_info* vol, 
     const int mode = opts ? opts->mode : CSGV_MODE_PLAIN;
     if (mode != CSGV_MODE_PLAIN && mode != CSGV_MODE_PERSISTENT) return fail(CSGV_EINVAL, "unknown mode %d", mode);
     Params P = make_params(vol, d_container, d_brick_ids, d_lods, d_out_offsets, n, d_out, out_capacity, d_status);
-    if (opts && opts->lds_slots > 0) P.cap16 = (uint32_t)opts->lds_slots;
+    if (opts && opts->lds_slots > 0) P.cap16 = std::max<uint32_t>((uint32_t)opts->lds_slots, kMinCap16);
     const int wg = opts && opts->wg_size ? opts->wg_size : 256;
     uint32_t grid = 1;
     if (mode == CSGV_MODE_PERSISTENT) {
@@ -336,7 +339,7 @@ uint32_t plan_grid(const csgv_plan* p, uint32_t n) {
 
 csgv_status plan_enqueue(csgv_plan* p, hipStream_t s, const Params& P0, bool with_events) {
     Params P = P0;
-    P.cap16 = (uint32_t)p->opts.lds_slots;
+    P.cap16 = std::max<uint32_t>((uint32_t)p->opts.lds_slots, kMinCap16);
     hipError_t e = enqueue_persistent(P, p->b, &p->vol, p->opts.wg_size, plan_grid(p, P.n_tasks),
                                       p->opts.sort_tasks != 0, s, with_events ? p->ev0 : nullptr,
                                       with_events ? p->ev1 : nullptr);
@@ -365,6 +368,14 @@ csgv_status plan_alloc(csgv_plan* p) {
     carve(p->mem, sb, p->max_tasks, &p->b);
     p->grid = grid;
     p->scratch_bytes = sb;
+    // the volume's rANS table, built once for every launch of the plan
+    bool ok;
+    const RansFreq f = pack_freq(&p->vol, &ok);
+    if (ok) {
+        if ((e = launch_rans_table(p->b.rans_tab, f, nullptr)) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess)
+            return fail(CSGV_EHIP, "rANS table: %s", hipGetErrorString(e));
+    }
+    p->b.table_built = true;
     return CSGV_OK;
 }
 
@@ -601,7 +612,7 @@ extern "C" csgv_status csgv_plan_autotune(csgv_plan* p, hipStream_t stream, cons
         return CSGV_OK;
     };
     static const int kWg[] = {128, 256, 512};
-    static const int kLds[] = {6144, 10240, 16384, 24576};
+    static const int kLds[] = {8192, 10240, 16384, 24576};
     float best_ms = 1e30f;
     csgv_decode_opts best = start;
     int tried = 0;

@@ -9,21 +9,25 @@
 namespace csgv {
 
 // ---- LDS of a decode work-group: a fixed part plus `cap16` 16-bit slots for
-// the explicit nodes of levels 4 and 5 (the LDS split chosen per launch).
+// the explicit nodes of level 5 (the LDS split chosen per launch).  The slot
+// area also holds the 16 KiB rANS decoding table while a record's symbols are
+// decoded, so it is never smaller than kMinCap16 slots.
 constexpr uint32_t kMaxWaves = 16;       // work-groups of up to 1024 threads
-constexpr uint32_t kFullSlots = 592;     // full grids of levels 0..3 at 0, 8, 16, 80
+constexpr uint32_t kFullSlots = 4688;    // full grids of levels 0..4 at 0, 8, 16, 80, 592
 constexpr uint32_t kEWords = 148;        // expansion bitmaps of levels 0..4: 1+1+2+16+128 words
-constexpr uint32_t kUBytes = 16384;      // rANS table | parent list + values | staged palette
-constexpr uint32_t kMaxCap16 = 32768;    // largest LDS slot share accepted
+constexpr uint32_t kUBytes = 8192;       // parent list of the level being decoded | staged palette
+constexpr uint32_t kMinCap16 = 8192;     // 16 KiB: the rANS table
+constexpr uint32_t kMaxCap16 = 32760;    // largest LDS slot share accepted
 constexpr uint32_t kDefaultCap16 = 10240;
 
 // ---- per work-group global scratch (byte offsets).  Big-path level storage
-// (32-bit slots), the level-5 bitmap used by 64^3 bricks, parent lists of
-// levels 6 (and every level on the big path), then the decoded rANS symbols
-// (4 bits each) whose size depends on the largest brick side of the volume.
-constexpr uint64_t kScrFull = 0;                                   // 592 x u32
-constexpr uint64_t kScrComp = 2560;                                // (4096 + 32768) x u32
-constexpr uint64_t kScrE5 = kScrComp + 4ull * (4096 + 32768);      // 1024 x u32
+// (32-bit slots: full grids of levels 0..4, level 5 by rank), the level-5
+// bitmap used by 64^3 bricks, parent lists of level 6 (and of every level on
+// the big path), then the decoded rANS symbols (4 bits each) whose size
+// depends on the largest brick side of the volume.
+constexpr uint64_t kScrFull = 0;                                   // 4688 x u32
+constexpr uint64_t kScrComp = 18944;                               // 32768 x u32
+constexpr uint64_t kScrE5 = kScrComp + 4ull * 32768;               // 1024 x u32
 constexpr uint64_t kScrWpre5 = kScrE5 + 4096;                      // 1024 x u16
 constexpr uint64_t kScrList = kScrWpre5 + 2048;                    // 32768 x u16
 constexpr uint64_t kScrPval = kScrList + 65536;                    // 32768 x u32
@@ -58,10 +62,11 @@ struct Params {
     const uint32_t* order;  // optional pop order
     uint8_t* scratch;
     uint64_t scratch_stride;
-    uint32_t cap16;     // LDS slots for the explicit nodes of levels 4 and 5
+    uint32_t cap16;     // LDS slots for the explicit nodes of level 5 (>= kMinCap16)
 };
 
 size_t shared_bytes(uint32_t cap16);
+int max_resident_per_cu(int wg_size, uint32_t cap16);  // occupancy of the decode kernel
 hipError_t set_kernel_attrs();
 hipError_t launch_decode(const Params& P, int wg_size, uint32_t grid, hipStream_t s);
 hipError_t launch_reset(uint32_t* q, hipStream_t s);

@@ -9,21 +9,23 @@
 // pipeline" for the decode stage; Methods > "Memory management" for LODs).
 //
 // Storage of the levels of a task (node order within a level is Morton):
-//   levels 0..3   full grids (585 nodes): implied nodes are filled with their
-//                 parent's value when the level starts;
-//   levels 4, 5   explicit nodes only, indexed by their operation rank k
-//                 (the k-th operation of a level is the k-th explicit node in
-//                 Morton order); an implied node is looked up through its
-//                 parent: rank of an expanding parent = prefix popcount of the
-//                 parent level's expansion bitmap;
+//   levels 0..4   full grids (4681 nodes).  When a level starts, the children
+//                 of every parent that does not expand take the parent's
+//                 value, and the children of expanding parents are marked
+//                 "not yet decoded";
+//   level 5       explicit nodes only, indexed by operation rank k (the k-th
+//                 operation of a level is the k-th explicit node in Morton
+//                 order); an implied node is its level-4 parent's value, an
+//                 explicit one is found through the rank of its parent:
+//                 prefix popcount of the level-4 expansion bitmap;
 //   level 6       (64^3 bricks at full resolution) explicit nodes are kept at
 //                 their voxel position in the task's own output range, which
 //                 the output pass then overwrites in place with labels.
 // A slot holds either a final palette index (top bit set) or a reference to
 // a same-level slot whose value it copies (a neighbour operation whose target
-// was decoded in the same pass).  Fast path: 16-bit slots, levels 0..5 in
-// LDS.  Big path (palettes above 2^15 entries or more explicit nodes than the
-// LDS share holds): 32-bit slots in a per-work-group global scratch area.
+// is decoded in the same pass).  Fast path: 16-bit slots, levels 0..5 in LDS.
+// Big path (palettes above 2^15 entries or more level-5 nodes than the LDS
+// share holds): 32-bit slots in a per-work-group global scratch area.
 //
 // A level's symbol segment is consumed in passes of one symbol per thread.
 // Per wavefront, ballots classify each symbol as an operation or a 4-bit
@@ -50,12 +52,18 @@
 namespace csgv {
 
 // ------------------------------------------------------------------ layout
-__device__ __forceinline__ uint32_t fbase(uint32_t i) { return i == 0 ? 0u : i == 1 ? 8u : i == 2 ? 16u : 80u; }
-__device__ __forceinline__ uint32_t ebase(uint32_t i) { return i == 0 ? 0u : i == 1 ? 1u : i == 2 ? 2u : i == 3 ? 4u : 20u; }
+// full grids of levels 0..4 at these slot offsets (8-aligned for 16-byte fills)
+__device__ __forceinline__ uint32_t fbase(uint32_t i) {
+    return i == 0 ? 0u : i == 1 ? 8u : i == 2 ? 16u : i == 3 ? 80u : 592u;
+}
+// expansion bitmaps of levels 0..4 at these word offsets
+__device__ __forceinline__ uint32_t ebase(uint32_t i) {
+    return i == 0 ? 0u : i == 1 ? 1u : i == 2 ? 2u : i == 3 ? 4u : 20u;
+}
 __host__ __device__ constexpr uint32_t ewords(uint32_t i) { return i <= 1 ? 1u : i == 2 ? 2u : (1u << (3 * i - 5)); }
 
 struct TaskHdr {
-    uint32_t task, status, write_ok, coder, L, t, log2W, pc, big, pal_lds, c5base, nsym;
+    uint32_t task, status, write_ok, coder, L, t, log2W, pc, big, pal_lds, nsym;
     uint32_t sym_end[7];
     uint32_t gw[4], gstart[4];
     uint64_t out_off, pal_off, pay_off, states_off;
@@ -66,12 +74,12 @@ struct Shared {
     uint32_t err;
     uint32_t pub[2][kMaxWaves];
     uint32_t red[kMaxWaves + 2];
-    uint32_t E[kEWords];       // expansion bitmaps of levels 0..4
-    uint16_t wpre[kEWords];    // exclusive popcount prefix of each bitmap word
-    alignas(16) uint16_t G[kFullSlots];  // full grids of levels 0..3 (fast path)
-    alignas(16) uint8_t U[kUBytes];      // rANS table | parent list + values | palette
+    uint32_t E[kEWords];                 // expansion bitmaps of levels 0..4
+    uint16_t wpre[kEWords];              // exclusive popcount prefix of each bitmap word
+    alignas(16) uint16_t G[kFullSlots];  // full grids of levels 0..4 (fast path)
+    alignas(16) uint8_t U[kUBytes];      // parent list of the level being decoded | staged palette
 };
-static_assert(sizeof(Shared) % 16 == 0, "compact slots follow Shared 16-byte aligned");
+static_assert(sizeof(Shared) % 16 == 0, "the slot area follows Shared 16-byte aligned");
 
 // ------------------------------------------------------ wave/block helpers
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
@@ -106,10 +114,6 @@ __device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t* total, 
         uint32_t o = __shfl_up(incl, d, 64);
         if (lane >= (uint32_t)d) incl += o;
     }
-    if (NT == 64) {
-        *total = __shfl(incl, 63, 64);
-        return incl - v;
-    }
     if (lane == 63) red[wave] = incl;
     __syncthreads();
     uint32_t base = 0, tot = 0;
@@ -132,13 +136,12 @@ __device__ __forceinline__ uint32_t fn_then(uint32_t first, uint32_t second) {
 }
 
 // -------------------------------------------------------------- palette
-__device__ __forceinline__ uint64_t pal_read(const Params& P, const TaskHdr& h, const uint8_t* U, uint32_t idx) {
-    if (P.label_bytes == 4) {
-        if (h.pal_lds) return ((const uint32_t*)U)[idx];
-        return idx < h.pc ? ((const uint32_t*)(P.vol + h.pal_off))[idx] : 0u;
-    }
-    if (h.pal_lds) return ((const uint64_t*)U)[idx];
-    return idx < h.pc ? ((const uint64_t*)(P.vol + h.pal_off))[idx] : 0u;
+// Palette entry idx: staged in LDS (PAL_LDS) or read from the record.  LT is
+// the label type (u32 or u64); a global read is bounded by the palette count.
+template <typename LT, bool PAL_LDS>
+__device__ __forceinline__ LT pal_get(const LT* pal, uint32_t idx, uint32_t pc) {
+    if (PAL_LDS) return pal[idx];
+    return idx < pc ? pal[idx] : (LT)0;
 }
 
 // -------------------------------------------------------------- task parse
@@ -146,7 +149,7 @@ __device__ __forceinline__ uint32_t ld32(const uint8_t* p) { return *(const uint
 
 // Validate task j and its record with the same checks, in the same order, as
 // the CPU decoder; fills the header (thread 0 only).
-__device__ void parse_task(const Params& P, uint32_t task, TaskHdr& h) {
+__device__ __forceinline__ void parse_task(const Params& P, uint32_t task, TaskHdr& h) {
     h.task = task;
     h.status = kTaskOk;
     h.write_ok = 0;
@@ -214,39 +217,35 @@ __device__ void parse_task(const Params& P, uint32_t task, TaskHdr& h) {
     h.pal_off = a + pal_rel;
     h.pay_off = a + pay_rel;
     h.nsym = h.sym_end[t];
-    // the explicit nodes of levels 4 and 5 are at most their segments' symbol counts
-    uint32_t need = 0, c5 = 0;
-    if (t >= 4) {
-        c5 = (h.sym_end[4] - h.sym_end[3] + 7u) & ~7u;
-        need = c5;
-        if (t >= 5) need += h.sym_end[5] - h.sym_end[4];
-    }
-    h.c5base = c5;
-    h.big = pc > 32768u || need > P.cap16;
+    // explicit nodes of level 5: at most one per symbol of its segment
+    const uint32_t need5 = t >= 5 ? h.sym_end[5] - h.sym_end[4] : 0u;
+    h.big = pc > 32768u || need5 > P.cap16;
     h.pal_lds = (uint64_t)pc * lb <= kUBytes;
 }
 
+
 // ----------------------------------------------------------------- rANS
 // Decode the first h.nsym symbols of the record into 4-bit symbols at nib[]
-// (low nibble first).  Wavefront w handles lane groups w, w + NW, ...
+// (low nibble first).  Wavefront w handles lane groups w, w + NW, ...  A
+// group's words sit in a 192-word register window; the third 64-word block is
+// fetched as soon as the window moves, one window move before it is needed.
 template <int NT>
-__device__ void rans_decode(const Params& P, Shared& sh, uint8_t* nib) {
+__device__ __forceinline__ void rans_decode(const Params& P, Shared& sh, const uint32_t* tab, uint8_t* nib) {
     const TaskHdr& h = sh.h;
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
     const uint32_t W = 1u << h.log2W, G = (W + 63) / 64, lanes = W < 64 ? W : 64;
     const uint32_t nsym = h.nsym;
     const uint16_t* words = (const uint16_t*)(P.vol + h.pay_off);
     const uint32_t* states = (const uint32_t*)(P.vol + h.states_off);
-    const uint32_t* tab = (const uint32_t*)sh.U;
     for (uint32_t g = wave; g < G; g += NT / 64) {
         const bool active = lane < lanes;
         const uint32_t gl = 64 * g + lane;
         const uint32_t gcount = h.gw[g], gbase = h.gstart[g];
         uint32_t x = active ? states[gl] : 0u;
-        // word window: win0 holds words [wbase, wbase+64), win1 the next 64
         uint32_t wbase = 0;
         uint32_t win0 = lane < gcount ? words[gbase + lane] : 0u;
         uint32_t win1 = 64 + lane < gcount ? words[gbase + 64 + lane] : 0u;
+        uint32_t win2 = 128 + lane < gcount ? words[gbase + 128 + lane] : 0u;
         uint32_t gpos = 0, pend = 0;
         bool bad = false;
         for (uint32_t r0 = 64 * g; r0 < nsym; r0 += W) {
@@ -261,7 +260,7 @@ __device__ void rans_decode(const Params& P, Shared& sh, uint8_t* nib) {
             const bool need = act && x < kRansL;
             const uint64_t m = __ballot(need);
             const uint32_t widx = gpos + mbcnt(m);
-            const uint32_t rel = widx - wbase;
+            const uint32_t rel = widx - wbase;  // < 128: at most 64 words per round, gpos - wbase < 64
             const uint32_t v0 = __shfl(win0, rel & 63, 64), v1 = __shfl(win1, rel & 63, 64);
             if (need) {
                 if (widx >= gcount) bad = true;
@@ -283,8 +282,9 @@ __device__ void rans_decode(const Params& P, Shared& sh, uint8_t* nib) {
             if (gpos - wbase >= 64) {
                 wbase += 64;
                 win0 = win1;
-                const uint32_t p = wbase + 64 + lane;
-                win1 = p < gcount ? words[gbase + p] : 0u;
+                win1 = win2;
+                const uint32_t p = wbase + 128 + lane;
+                win2 = p < gcount ? words[gbase + p] : 0u;
             }
         }
         if (__ballot(bad) && lane == 0) atomicOr(&sh.err, 1u);
@@ -292,359 +292,358 @@ __device__ void rans_decode(const Params& P, Shared& sh, uint8_t* nib) {
 }
 
 // ------------------------------------------------------------ level store
-// Where the levels of one task live.  V: slot type (u16 fast path, u32 big
-// path).  Full grids of levels 0..3 and compact slots of levels 4 and 5 are
-// LDS (fast) or scratch (big); level 6 slots are u32 at the voxel position in
-// the output; parent lists are LDS for levels <= 5 on the fast path.
 template <typename V>
 struct Slot {
     static constexpr V kFinal = (V)(V(1) << (sizeof(V) * 8 - 1));
     static constexpr V kIdx = (V)(kFinal - 1);
+    static constexpr V kNotYet = kIdx;  // explicit node whose operation is not decoded yet (full levels)
 };
 
-template <typename V, bool BIG>
+// Where the levels of one task live.  V: slot type (u16 fast path, u32 big
+// path).  Full grids of levels 0..4 and the compact level 5 are LDS (fast) or
+// scratch (big); level-6 slots are u32 at the voxel position in the output.
+template <typename V>
 struct Store {
-    V* full;          // levels 0..3 at fbase(i)
-    V* c4;            // compact slots of level 4
-    V* c5;            // compact slots of level 5
-    uint32_t* out6;   // level-6 slots (u32 at voxel v: out6[v * lb / 4])
+    V* full;          // levels 0..4 at fbase(i)
+    V* c5;            // level-5 explicit nodes by operation rank
+    uint32_t* out6;   // level-6 slot of voxel v: out6[v * lb4]
     uint32_t lb4;     // label_bytes / 4
     uint32_t* E;      // bitmaps of levels 0..4 (LDS)
     uint16_t* wpre;
-    uint32_t* E5;     // bitmap of level 5 (scratch)
+    uint32_t* E5;     // bitmap of level 5 (scratch; 64^3 bricks at full resolution)
     uint16_t* wpre5;
-    uint16_t* list_l;  // parent lists in LDS (fast path, levels <= 5)
-    V* pval_l;
-    uint16_t* list_g;  // parent lists in scratch
-    uint32_t* pval_g;
-    bool list_in_lds;
+    uint16_t* list_l;  // parents of the level being decoded, LDS (levels 1..5 on the fast path)
+    uint16_t* list_g;  // the same in scratch (level 6, big path)
+    uint32_t* pval_g;  // values of level-6 parents (scratch)
 
-    __device__ __forceinline__ uint32_t* ebits(uint32_t lvl) const { return lvl <= 4 ? E + ebase(lvl) : E5; }
-    __device__ __forceinline__ const uint16_t* epre(uint32_t lvl) const { return lvl <= 4 ? wpre + ebase(lvl) : wpre5; }
+    // expansion bit / rank among the expanding nodes of a level: levels 0..4 in LDS ...
     __device__ __forceinline__ bool ebit(uint32_t lvl, uint32_t q) const {
-        if (lvl <= 4) return (E[ebase(lvl) + (q >> 5)] >> (q & 31)) & 1u;
-        return (E5[q >> 5] >> (q & 31)) & 1u;
+        return (E[ebase(lvl) + (q >> 5)] >> (q & 31)) & 1u;
     }
     __device__ __forceinline__ uint32_t rank(uint32_t lvl, uint32_t q) const {
-        uint32_t w, p;
-        if (lvl <= 4) {
-            w = E[ebase(lvl) + (q >> 5)];
-            p = wpre[ebase(lvl) + (q >> 5)];
-        } else {
-            w = E5[q >> 5];
-            p = wpre5[q >> 5];
-        }
-        return p + (uint32_t)__popc(w & ((1u << (q & 31)) - 1u));
+        const uint32_t w = E[ebase(lvl) + (q >> 5)];
+        return wpre[ebase(lvl) + (q >> 5)] + (uint32_t)__popc(w & ((1u << (q & 31)) - 1u));
     }
-    // value of node `node` of level lvl (<= 5), all levels up to lvl final
-    __device__ __forceinline__ uint32_t value_at(uint32_t lvl, uint32_t node) const {
-        while (lvl >= 4) {
-            const uint32_t q = node >> 3;
-            if (ebit(lvl - 1, q)) {
-                const uint32_t k = 8 * rank(lvl - 1, q) + (node & 7);
-                return lvl == 4 ? (uint32_t)c4[k] : (uint32_t)c5[k];
-            }
-            lvl -= 1;
-            node = q;
-        }
-        return full[fbase(lvl) + node];
+    // ... and level 5 in scratch
+    __device__ __forceinline__ bool ebit5(uint32_t q) const { return (E5[q >> 5] >> (q & 31)) & 1u; }
+    __device__ __forceinline__ uint32_t rank5(uint32_t q) const {
+        return wpre5[q >> 5] + (uint32_t)__popc(E5[q >> 5] & ((1u << (q & 31)) - 1u));
     }
-    // slot of level lvl at index idx (full: node; compact: rank; level 6: voxel)
-    __device__ __forceinline__ uint32_t get(uint32_t lvl, uint32_t idx) const {
-        if (lvl <= 3) return full[fbase(lvl) + idx];
-        if (lvl == 4) return c4[idx];
-        if (lvl == 5) return c5[idx];
-        return out6[(uint64_t)idx * lb4];
-    }
-    __device__ __forceinline__ void set(uint32_t lvl, uint32_t idx, uint32_t v) const {
-        if (lvl <= 3) full[fbase(lvl) + idx] = (V)v;
-        else if (lvl == 4) c4[idx] = (V)v;
-        else if (lvl == 5) c5[idx] = (V)v;
-        else out6[(uint64_t)idx * lb4] = v;
-    }
-    __device__ __forceinline__ uint32_t list(uint32_t r) const { return list_in_lds ? list_l[r] : list_g[r]; }
-    __device__ __forceinline__ uint32_t pval(uint32_t r) const { return list_in_lds ? (uint32_t)pval_l[r] : pval_g[r]; }
-    __device__ __forceinline__ void set_list(uint32_t r, uint32_t q, uint32_t v) const {
-        if (list_in_lds) {
-            list_l[r] = (uint16_t)q;
-            pval_l[r] = (V)v;
-        } else {
-            list_g[r] = (uint16_t)q;
-            pval_g[r] = v;
-        }
+    // value of a level-5 node (levels 0..5 final)
+    __device__ __forceinline__ uint32_t value5(uint32_t node) const {
+        const uint32_t q = node >> 3;
+        if (ebit(4, q)) return c5[8 * rank(4, q) + (node & 7)];
+        return full[fbase(4) + q];
     }
 };
 
-// final flag / index mask of a level's slots (level 6 slots are always u32)
-template <typename V>
-__device__ __forceinline__ uint32_t fin_bit(uint32_t lvl) { return lvl == 6 ? 0x80000000u : (uint32_t)Slot<V>::kFinal; }
-
-// index of node p (Morton, level i) in the level's slot storage given its op rank k
-__device__ __forceinline__ uint32_t slot_index(uint32_t i, uint32_t p, uint32_t k) {
-    if (i <= 3) return p;
-    if (i <= 5) return k;
-    return (compact3(p >> 2) << 12) | (compact3(p >> 1) << 6) | compact3(p);  // (z*64 + y)*64 + x
+// voxel index (z*64 + y)*64 + x of a level-6 Morton index
+__device__ __forceinline__ uint32_t vox6(uint32_t p) {
+    return (compact3(p >> 2) << 12) | (compact3(p >> 1) << 6) | compact3(p);
 }
 
-// ------------------------------------------------------------ level decode
-template <int NT, typename V, bool BIG>
-__device__ void decode_levels(const Params& P, Shared& sh, const Store<V, BIG>& st, const uint8_t* nib) {
+// ------------------------------------------------------------ level set-up
+// Expanding parents of level i-1 (i >= 1): exclusive popcount prefix of their
+// bitmap words, the list of their node indices by rank, and (full level i)
+// the children's initial slots.  Returns the number of expanding parents.
+template <int NT, typename V, bool BIG, bool LIST_LDS, bool PL5>
+__device__ __forceinline__ uint32_t level_setup(Shared& sh, const Store<V>& st, uint32_t i, uint32_t t) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t pl = i - 1, pn = 1u << (3 * pl), pw = ewords(pl);
+    // parents' bitmap: levels 0..4 in LDS, level 5 in scratch
+    uint32_t* const Ep = PL5 ? st.E5 : st.E + ebase(pl);
+    uint16_t* const Wp = PL5 ? st.wpre5 : st.wpre + ebase(pl);
+    uint32_t base = 0;
+    for (uint32_t w0 = 0; w0 < pw; w0 += NT) {
+        const uint32_t w = w0 + tid;
+        uint32_t bits = w < pw ? Ep[w] : 0u;
+        if (pn < 32) bits &= (1u << pn) - 1u;
+        uint32_t tot;
+        const uint32_t pre = block_excl_sum<NT>((uint32_t)__popc(bits), &tot, sh.red);
+        if (w < pw) Wp[w] = (uint16_t)(base + pre);
+        base += tot;
+    }
+    __syncthreads();
+    constexpr V NOTYET = Slot<V>::kNotYet;
+    for (uint32_t q = tid; q < pn; q += NT) {
+        const uint32_t bits = Ep[q >> 5] & (pn < 32 ? (1u << pn) - 1u : 0xFFFFFFFFu);
+        const bool ex = (bits >> (q & 31)) & 1u;
+        if (ex) {
+            const uint32_t r = Wp[q >> 5] + (uint32_t)__popc(bits & ((1u << (q & 31)) - 1u));
+            if (LIST_LDS) {
+                st.list_l[r] = (uint16_t)q;
+            } else {
+                st.list_g[r] = (uint16_t)q;
+                if (PL5) st.pval_g[r] = st.value5(q);
+            }
+        }
+        if (!PL5 && i <= 4) {
+            const V v = ex ? NOTYET : st.full[fbase(pl) + q];
+            V* d = st.full + fbase(i) + 8 * q;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) d[c] = v;
+        }
+    }
+    if (i < t) {
+        if (i <= 4) {
+            for (uint32_t w = tid; w < ewords(i); w += NT) st.E[ebase(i) + w] = 0;
+        } else {
+            for (uint32_t w = tid; w < ewords(5); w += NT) st.E5[w] = 0;
+        }
+    }
+    __syncthreads();
+    return base;
+}
+
+// ------------------------------------------------------------ level passes
+// KIND 0: full level (i <= 4), 1: compact level 5, 2: level 6 in the output.
+template <int NT, int KIND, typename V, bool BIG, bool LIST_LDS>
+__device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const Store<V>& st, const uint8_t* nib, uint32_t i,
+                             uint32_t expected, uint32_t& adv_done, uint32_t& pbuf) {
     constexpr uint32_t NW = NT / 64;
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const uint32_t t = sh.h.t, pc = sh.h.pc;
-    uint32_t adv_done = 0;
-    uint32_t pbuf = 0;
-    for (uint32_t i = 0; i <= t; ++i) {
-        const uint32_t nodes = 1u << (3 * i);
-        const uint32_t FIN = fin_bit<V>(i), IDX = FIN - 1u;
-        // final values of lower levels carry V's flag; level-6 slots are u32 with their own
-        const auto refin = [FIN](uint32_t x) { return (x & (uint32_t)Slot<V>::kIdx) | FIN; };
-        // references of this level point below this bound (full: nodes; compact: ops; level 6: voxels)
-        const uint32_t ref_lim = i <= 3 ? nodes : i <= 5 ? 0xFFFFFFFFu : (1u << 18);
-        // ------------------------------------------ level set-up
-        uint32_t expected = 1;
-        if (i > 0) {
-            // expanding parents of level i-1: word prefix, list, values
-            const uint32_t pl = i - 1, pn = nodes >> 3, pw = ewords(pl);
-            uint32_t* Ep = st.ebits(pl);
-            uint16_t* Wp = (uint16_t*)st.epre(pl);
-            uint32_t base = 0;
-            for (uint32_t w0 = 0; w0 < pw; w0 += NT) {
-                const uint32_t w = w0 + tid;
-                uint32_t bits = w < pw ? Ep[w] : 0u;
-                if (pn < 32) bits &= (1u << pn) - 1u;
-                uint32_t tot;
-                const uint32_t pre = block_excl_sum<NT>((uint32_t)__popc(bits), &tot, sh.red);
-                if (w < pw) {
-                    Wp[w] = (uint16_t)(base + pre);
-                    if (pn < 32) Ep[w] = bits;
-                }
-                base += tot;
-            }
-            expected = 8 * base;
-            __syncthreads();
-            for (uint32_t q = tid; q < pn; q += NT) {
-                const uint32_t bits = Ep[q >> 5];
-                const bool ex = (bits >> (q & 31)) & 1u;
-                if (ex) {
-                    const uint32_t r = Wp[q >> 5] + (uint32_t)__popc(bits & ((1u << (q & 31)) - 1u));
-                    st.set_list(r, q, st.value_at(pl, q));
-                } else if (i <= 3) {
-                    const uint32_t v = st.full[fbase(pl) + q];
-                    V* d = st.full + fbase(i) + 8 * q;
-#pragma unroll
-                    for (int c = 0; c < 8; ++c) d[c] = (V)v;
-                }
-            }
+    const uint32_t nodes = 1u << (3 * i);
+    // final flag of this level's slots (level 6 slots are always u32)
+    constexpr uint32_t FIN = KIND == 2 ? 0x80000000u : (uint32_t)Slot<V>::kFinal;
+    constexpr uint32_t IDX = FIN - 1u;
+    constexpr uint32_t VIDX = (uint32_t)Slot<V>::kIdx;
+    V* const full_i = st.full + (KIND == 0 ? fbase(i) : 0u);
+    const V* const full_p = st.full + (i ? fbase(i <= 5 ? i - 1 : 4) : 0u);
+    // expansion bits of this level (needed when t > i): LDS for full levels, scratch for level 5
+    uint32_t* const Ei_l = KIND == 0 && i < t ? st.E + ebase(i) : nullptr;
+    uint32_t* const Ei_g = KIND == 1 && i < t ? st.E5 : nullptr;
+    const uint32_t mx = 0x09249249u & (nodes - 1u), my = mx << 1, mz = mx << 2;
+    const uint32_t s0 = i ? sh.h.sym_end[i - 1] : 0u, s1 = sh.h.sym_end[i];
+    uint32_t carry = 0, k_done = 0;
+    bool bad = false;
+    uint32_t snext = 0;
+    if (s0 + tid < s1) {
+        const uint32_t j = s0 + tid;
+        snext = (nib[j >> 1] >> (4 * (j & 1))) & 15u;
+    }
+    for (uint32_t c = s0; c < s1; c += NT) {
+        const uint32_t j = c + tid;
+        const bool valid = j < s1;
+        const uint32_t s = snext;
+        if (j + NT < s1) {
+            const uint32_t jn = j + NT;
+            snext = (nib[jn >> 1] >> (4 * (jn & 1))) & 15u;
         }
-        if (i < t && i <= 5) {
-            uint32_t* Ei = st.ebits(i);
-            for (uint32_t w = tid; w < ewords(i); w += NT) Ei[w] = 0;
+        // classification for both entry states
+        const uint64_t m_valid = __ballot(valid);
+        const uint64_t m_cand = __ballot(valid && (s & 7u) == kDelta);
+        const uint64_t m_adv = __ballot(valid && (s & 7u) == kAdv);
+        uint64_t ops0, ops1;
+        uint32_t x0, x1;
+        if (m_cand == 0) {
+            ops0 = m_valid;
+            x0 = 0;
+            const uint64_t m_end = m_valid & ~__ballot(valid && (s & 8u));
+            if (m_end) {
+                const uint32_t f = (uint32_t)__builtin_ctzll(m_end);
+                const uint64_t upto = f >= 63 ? ~0ull : ((2ull << f) - 1ull);
+                ops1 = m_valid & ~upto;
+                x1 = 0;
+            } else {
+                ops1 = 0;
+                x1 = 1;
+            }
+        } else {
+            const uint32_t f = valid ? (((s & 7u) == kDelta ? 1u : 0u) | (((s >> 3) & 1u) << 1)) : 2u;
+            uint32_t incl = f;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t o = __shfl_up(incl, d, 64);
+                if (lane >= (uint32_t)d) incl = fn_then(o, incl);
+            }
+            uint32_t excl = __shfl_up(incl, 1, 64);
+            if (lane == 0) excl = 2u;
+            ops0 = __ballot(valid && !(excl & 1u));
+            ops1 = __ballot(valid && !((excl >> 1) & 1u));
+            const uint32_t tot = __shfl(incl, 63, 64);
+            x0 = tot & 1u;
+            x1 = (tot >> 1) & 1u;
+        }
+        if (lane == 0) {
+            sh.pub[pbuf][wave] = (uint32_t)__popcll(ops0) | ((uint32_t)__popcll(ops1) << 7) |
+                                 ((uint32_t)__popcll(ops0 & m_adv) << 14) | ((uint32_t)__popcll(ops1 & m_adv) << 21) |
+                                 (x0 << 28) | (x1 << 29);
         }
         __syncthreads();
-        // ------------------------------------------ passes over the segment
-        const uint32_t mx = 0x09249249u & (nodes - 1u), my = mx << 1, mz = mx << 2;
-        const uint32_t s0 = i ? sh.h.sym_end[i - 1] : 0u, s1 = sh.h.sym_end[i];
-        uint32_t carry = 0, k_done = 0;
-        bool bad = false;
-        uint32_t snext = 0;
-        if (s0 + tid < s1) {
-            const uint32_t j = s0 + tid;
-            snext = (nib[j >> 1] >> (4 * (j & 1))) & 15u;
+        // fold the waves' summaries: this wave's entry state, op base, ADV base; pass totals
+        uint32_t e = carry, kb = k_done, ab = adv_done, my_e = 0, my_kb = 0, my_ab = 0;
+#pragma unroll
+        for (uint32_t w = 0; w < NW; ++w) {
+            if (w == wave) {
+                my_e = e;
+                my_kb = kb;
+                my_ab = ab;
+            }
+            const uint32_t p = sh.pub[pbuf][w];
+            const uint32_t q = e ? (p >> 7) : p;
+            kb += q & 127u;
+            ab += (q >> 14) & 127u;
+            e = (p >> (28 + e)) & 1u;
         }
-        for (uint32_t c = s0; c < s1; c += NT) {
-            const uint32_t j = c + tid;
-            const bool valid = j < s1;
-            const uint32_t s = snext;
-            if (j + NT < s1) {
-                const uint32_t jn = j + NT;
-                snext = (nib[jn >> 1] >> (4 * (jn & 1))) & 15u;
-            }
-            // classification for both entry states
-            const uint64_t m_valid = __ballot(valid);
-            const uint64_t m_cand = __ballot(valid && (s & 7u) == kDelta);
-            const uint64_t m_adv = __ballot(valid && (s & 7u) == kAdv);
-            uint64_t ops0, ops1;
-            uint32_t x0, x1;
-            if (m_cand == 0) {
-                ops0 = m_valid;
-                x0 = 0;
-                const uint64_t m_end = m_valid & ~__ballot(valid && (s & 8u));
-                if (m_end) {
-                    const uint32_t f = (uint32_t)__builtin_ctzll(m_end);
-                    const uint64_t upto = f >= 63 ? ~0ull : ((2ull << f) - 1ull);
-                    ops1 = m_valid & ~upto;
-                    x1 = 0;
-                } else {
-                    ops1 = 0;
-                    x1 = 1;
-                }
+        const uint32_t k0 = k_done;
+        carry = e;
+        k_done = kb;
+        adv_done = ab;
+        pbuf ^= 1u;
+        const uint64_t my_ops = my_e ? ops1 : ops0;
+        uint32_t myidx = 0, myval = 0;
+        bool is_ref = false;
+        if ((my_ops >> lane) & 1u) {
+            const uint32_t k = my_kb + mbcnt(my_ops);
+            const uint32_t a = my_ab + mbcnt(my_ops & m_adv);
+            const uint32_t op = s & 7u;
+            if (k >= expected) {
+                bad = true;
             } else {
-                const uint32_t f = valid ? (((s & 7u) == kDelta ? 1u : 0u) | (((s >> 3) & 1u) << 1)) : 2u;
-                uint32_t incl = f;
-#pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    const uint32_t o = __shfl_up(incl, d, 64);
-                    if (lane >= (uint32_t)d) incl = fn_then(o, incl);
-                }
-                uint32_t excl = __shfl_up(incl, 1, 64);
-                if (lane == 0) excl = 2u;
-                ops0 = __ballot(valid && !(excl & 1u));
-                ops1 = __ballot(valid && !((excl >> 1) & 1u));
-                const uint32_t tot = __shfl(incl, 63, 64);
-                x0 = tot & 1u;
-                x1 = (tot >> 1) & 1u;
-            }
-            if (lane == 0) {
-                sh.pub[pbuf][wave] = (uint32_t)__popcll(ops0) | ((uint32_t)__popcll(ops1) << 7) |
-                                     ((uint32_t)__popcll(ops0 & m_adv) << 14) |
-                                     ((uint32_t)__popcll(ops1 & m_adv) << 21) | (x0 << 28) | (x1 << 29);
-            }
-            __syncthreads();
-            // fold the waves' summaries: entry state, op base and ADV base of this wave; pass totals
-            uint32_t e = carry, kb = k_done, ab = adv_done, my_e = 0, my_kb = 0, my_ab = 0;
-#pragma unroll
-            for (uint32_t w = 0; w < NW; ++w) {
-                if (w == wave) {
-                    my_e = e;
-                    my_kb = kb;
-                    my_ab = ab;
-                }
-                const uint32_t p = sh.pub[pbuf][w];
-                kb += e ? ((p >> 7) & 127u) : (p & 127u);
-                ab += e ? ((p >> 21) & 127u) : ((p >> 14) & 127u);
-                e = e ? ((p >> 29) & 1u) : ((p >> 28) & 1u);
-            }
-            const uint32_t k0 = k_done;
-            carry = e;
-            k_done = kb;
-            adv_done = ab;
-            pbuf ^= 1u;
-            const uint64_t my_ops = my_e ? ops1 : ops0;
-            const bool is_op = (my_ops >> lane) & 1u;
-            uint32_t myidx = 0, myval = 0;
-            bool is_ref = false;
-            if (is_op) {
-                const uint32_t k = my_kb + mbcnt(my_ops);
-                const uint32_t a = my_ab + mbcnt(my_ops & m_adv);
-                const uint32_t op = s & 7u, stop = s >> 3;
-                if (k >= expected) {
-                    bad = true;
-                } else {
-                    const uint32_t r = k >> 3;
-                    const uint32_t pn = i ? st.list(r) : 0u;
-                    const uint32_t p = i ? ((pn << 3) | (k & 7u)) : 0u;
-                    uint32_t v = FIN;
-                    switch (op) {
-                    case kParent:
-                        if (i == 0) bad = true;
-                        else v = refin(st.pval(r));
-                        break;
-                    case kNX:
-                    case kNY:
-                    case kNZ: {
-                        const uint32_t am = op == kNX ? mx : op == kNY ? my : mz;
-                        if (!(p & am)) {
+                const uint32_t r = k >> 3;
+                const uint32_t pn = i ? (LIST_LDS ? (uint32_t)st.list_l[r] : (uint32_t)st.list_g[r]) : 0u;
+                const uint32_t p = i ? ((pn << 3) | (k & 7u)) : 0u;
+                myidx = KIND == 0 ? p : KIND == 1 ? k : vox6(p);
+                uint32_t v = FIN;
+                if (op == kParent) {
+                    if (i == 0) bad = true;
+                    else if (KIND == 2) v = (st.pval_g[r] & VIDX) | FIN;
+                    else v = full_p[pn];
+                } else if (op <= kNZ) {
+                    const uint32_t am = op == kNX ? mx : op == kNY ? my : mz;
+                    if (!(p & am)) {
+                        bad = true;
+                    } else {
+                        const uint32_t tn = (((p & am) - 1u) & am) | (p & ~am);
+                        if (KIND == 0) {
+                            // implied targets hold their parent's value, explicit ones of earlier
+                            // passes their final value, those of this pass "not yet" or a reference
+                            v = full_i[tn];
+                            if (v == (uint32_t)Slot<V>::kNotYet) v = tn;
+                        } else {
+                            const uint32_t tq = tn >> 3;
+                            if (KIND == 1 ? !st.ebit(4, tq) : !st.ebit5(tq)) {
+                                v = KIND == 1 ? (uint32_t)full_p[tq] : ((st.value5(tq) & VIDX) | FIN);
+                            } else {
+                                const uint32_t kt = 8 * (KIND == 1 ? st.rank(4, tq) : st.rank5(tq)) + (tn & 7u);
+                                const uint32_t ti = KIND == 1 ? kt : vox6(tn);
+                                if (kt < k0) v = KIND == 1 ? (uint32_t)st.c5[ti] : st.out6[(uint64_t)ti * st.lb4];
+                                else v = ti;
+                            }
+                        }
+                        is_ref = !(v & FIN);
+                    }
+                } else if (op == kAdv) {
+                    if (a >= pc) bad = true;
+                    else v = FIN | a;
+                } else if (op == kLast) {
+                    if (a == 0) bad = true;
+                    else v = FIN | (a - 1u);
+                } else if (op == kDelta) {
+                    uint32_t d = 0, jj = j + 1, en = 8;
+                    while (en & 8u) {
+                        if (jj >= s1) {
                             bad = true;
                             break;
                         }
-                        const uint32_t tn = ((((p & am) - 1u) & am) | (p & ~am));
-                        const uint32_t tq = tn >> 3;
-                        if (!st.ebit(i - 1, tq)) {
-                            v = refin(st.value_at(i - 1, tq));  // implied target: its parent's value, final
-                        } else {
-                            const uint32_t kt = 8 * st.rank(i - 1, tq) + (tn & 7u);
-                            const uint32_t ti = slot_index(i, tn, kt);
-                            if (kt < k0) {
-                                v = st.get(i, ti);  // decoded in an earlier pass: final
-                            } else {
-                                v = ti;  // same pass: resolved below
-                                is_ref = true;
-                            }
-                        }
-                        break;
+                        en = (nib[jj >> 1] >> (4 * (jj & 1))) & 15u;
+                        d = d >= (1u << 29) ? 0xFFFFFFFFu : ((d << 3) | (en & 7u));
+                        ++jj;
                     }
-                    case kAdv:
-                        if (a >= pc) bad = true;
-                        else v = FIN | a;
-                        break;
-                    case kLast:
-                        if (a == 0) bad = true;
-                        else v = FIN | (a - 1u);
-                        break;
-                    case kDelta: {
-                        uint32_t d = 0, jj = j + 1, en = 8;
-                        while (en & 8u) {
-                            if (jj >= s1) {
-                                bad = true;
-                                break;
-                            }
-                            en = (nib[jj >> 1] >> (4 * (jj & 1))) & 15u;
-                            d = d >= (1u << 29) ? 0xFFFFFFFFu : ((d << 3) | (en & 7u));
-                            ++jj;
-                        }
-                        if (d == 0 || d > a) bad = true;
-                        else v = FIN | (a - d);
-                        break;
-                    }
-                    default:
-                        bad = true;
-                    }
-                    myidx = slot_index(i, p, k);
-                    myval = v;
-                    // written even after an error, so that a later lookup never meets an unset slot
-                    st.set(i, myidx, (is_ref && bad) ? FIN : v);
-                    if (i < t && !stop) atomicOr(st.ebits(i) + (p >> 5), 1u << (p & 31));
+                    if (d == 0 || d > a) bad = true;
+                    else v = FIN | (a - d);
+                } else {
+                    bad = true;
+                }
+                if (bad) {
+                    v = FIN;
+                    is_ref = false;
+                }
+                myval = v;
+                // written even after an error, so that a later lookup never meets an unset slot
+                if (KIND == 0) full_i[myidx] = (V)v;
+                else if (KIND == 1) st.c5[myidx] = (V)v;
+                else st.out6[(uint64_t)myidx * st.lb4] = v;
+                if (!(s & 8u)) {
+                    if (Ei_l) atomicOr(Ei_l + (p >> 5), 1u << (p & 31));
+                    if (Ei_g) atomicOr(Ei_g + (p >> 5), 1u << (p & 31));
                 }
             }
+        }
+        __syncthreads();
+        // references within the pass: chase to a final value
+        if (is_ref) {
+            const uint32_t lim = KIND == 0 ? nodes : KIND == 1 ? k_done : (1u << 18);
+            uint32_t v = myval, it = 0;
+            while (!(v & FIN)) {
+                if ((v & IDX) >= lim || ++it > NT) {
+                    bad = true;
+                    v = FIN;
+                    break;
+                }
+                v = KIND == 0 ? (uint32_t)full_i[v] : KIND == 1 ? (uint32_t)st.c5[v] : st.out6[(uint64_t)v * st.lb4];
+            }
+            if (KIND == 0) full_i[myidx] = (V)v;
+            else if (KIND == 1) st.c5[myidx] = (V)v;
+            else st.out6[(uint64_t)myidx * st.lb4] = v;
+        }
+    }
+    if (bad) atomicOr(&sh.err, 1u);
+    if ((k_done != expected || carry != 0) && tid == 0) sh.err = 1u;
+}
+
+// Decode levels 0..t; on return all slots of level t are final unless sh.err.
+template <int NT, typename V, bool BIG, bool LIST_LDS>
+__device__ __forceinline__ void decode_levels(const Params& P, Shared& sh, const Store<V>& st, const uint8_t* nib) {
+    const uint32_t t = sh.h.t;
+    uint32_t adv_done = 0, pbuf = 0;
+    for (uint32_t i = 0; i <= t; ++i) {
+        uint32_t expected = 1;
+        if (i == 0) {
+            if (t > 0 && threadIdx.x == 0) st.E[ebase(0)] = 0;
             __syncthreads();
-            // references within the pass: chase to a final value
-            if (is_ref && !bad) {
-                uint32_t v = myval, it = 0;
-                while (!(v & FIN)) {
-                    // a reference names an operation of this pass (compact levels: rank below k_done)
-                    if ((v & IDX) >= (i <= 3 || i == 6 ? ref_lim : k_done) || ++it > NT) {
-                        bad = true;
-                        break;
-                    }
-                    v = st.get(i, v & IDX);
-                }
-                if (!bad) st.set(i, myidx, v);
-                else st.set(i, myidx, FIN);
-            }
+        } else if (i <= 5) {
+            expected = 8 * level_setup<NT, V, BIG, LIST_LDS, false>(sh, st, i, t);
+        } else {
+            expected = 8 * level_setup<NT, V, BIG, false, true>(sh, st, i, t);
         }
-        if (bad) atomicOr(&sh.err, 1u);
-        if (k_done != expected || carry != 0) {
-            if (tid == 0) sh.err = 1u;
-        }
+        if (i <= 4) level_passes<NT, 0, V, BIG, LIST_LDS>(P, sh, st, nib, i, expected, adv_done, pbuf);
+        else if (i == 5) level_passes<NT, 1, V, BIG, LIST_LDS>(P, sh, st, nib, i, expected, adv_done, pbuf);
+        else level_passes<NT, 2, V, BIG, false>(P, sh, st, nib, i, expected, adv_done, pbuf);
         __syncthreads();
         if (sh.err) return;
     }
-    if (t == sh.h.L && adv_done != pc && tid == 0) sh.err = 1u;
+    if (t == sh.h.L && adv_done != sh.h.pc && threadIdx.x == 0) sh.err = 1u;
     __syncthreads();
 }
 
 // ------------------------------------------------------------------ output
-__device__ __forceinline__ void store_pair(uint8_t* out, uint32_t lb, uint64_t e, uint64_t l0, uint64_t l1, bool vec) {
-    if (lb == 4) {
-        uint32_t* o = (uint32_t*)out + e;
-        if (vec) *(uint2*)o = make_uint2((uint32_t)l0, (uint32_t)l1);
+template <typename LT>
+__device__ __forceinline__ void store4(LT* o, LT a, LT b, LT c, LT d, bool vec) {
+    if (sizeof(LT) == 4) {
+        if (vec) *(uint4*)o = make_uint4((uint32_t)a, (uint32_t)b, (uint32_t)c, (uint32_t)d);
         else {
-            o[0] = (uint32_t)l0;
-            o[1] = (uint32_t)l1;
+            o[0] = a;
+            o[1] = b;
+            o[2] = c;
+            o[3] = d;
         }
     } else {
-        uint64_t* o = (uint64_t*)out + e;
-        if (vec) *(uint4*)o = make_uint4((uint32_t)l0, (uint32_t)(l0 >> 32), (uint32_t)l1, (uint32_t)(l1 >> 32));
-        else {
-            o[0] = l0;
-            o[1] = l1;
+        if (vec) {
+            ((uint4*)o)[0] = make_uint4((uint32_t)a, (uint32_t)((uint64_t)a >> 32), (uint32_t)b, (uint32_t)((uint64_t)b >> 32));
+            ((uint4*)o)[1] = make_uint4((uint32_t)c, (uint32_t)((uint64_t)c >> 32), (uint32_t)d, (uint32_t)((uint64_t)d >> 32));
+        } else {
+            o[0] = a;
+            o[1] = b;
+            o[2] = c;
+            o[3] = d;
         }
     }
 }
 
 template <int NT>
-__device__ void zero_output(const Params& P, const TaskHdr& h) {
+__device__ __forceinline__ void zero_output(const Params& P, const TaskHdr& h) {
     const uint32_t t = h.t;
     const uint64_t n = 1ull << (3 * t);
     uint8_t* out = P.out + h.out_off * P.label_bytes;
@@ -656,104 +655,126 @@ __device__ void zero_output(const Params& P, const TaskHdr& h) {
     }
 }
 
-// Labels of level t (all slots final) as an S^3 x-fastest cube.  Levels
-// 0..3 voxel by voxel; levels 4..6 by 2x2x2 blocks under each node q of
-// level t-1: q's value when it does not expand, else its 8 children's slots.
-template <int NT, typename V, bool BIG>
-__device__ void write_output(const Params& P, Shared& sh, const Store<V, BIG>& st) {
+// Labels of level t (all slots final) as an S^3 x-fastest cube.  Full levels
+// voxel by voxel (4 per thread); levels 5 and 6 by pairs of 2x2x2 blocks
+// along x under two level-(t-1) nodes: a node that does not expand gives its
+// value to its 8 children, an expanding one has 8 explicit children.
+template <int NT, typename V, typename LT, bool PAL_LDS>
+__device__ __forceinline__ void write_labels(const Params& P, Shared& sh, const Store<V>& st) {
     const TaskHdr& h = sh.h;
-    const uint32_t t = h.t, S = 1u << t, lb = P.label_bytes;
-    const uint32_t IDXV = (uint32_t)Slot<V>::kIdx;
-    uint8_t* out = P.out + h.out_off * lb;
-    if (t <= 3) {
-        const uint32_t n = S * S * S;
-        for (uint32_t v = threadIdx.x; v < n; v += NT) {
-            const uint32_t x = v & (S - 1), y = (v >> t) & (S - 1), z = v >> (2 * t);
+    const uint32_t t = h.t, S = 1u << t, pc = h.pc;
+    constexpr uint32_t VIDX = (uint32_t)Slot<V>::kIdx;
+    LT* out = (LT*)(P.out + h.out_off * sizeof(LT));
+    const LT* pal = PAL_LDS ? (const LT*)sh.U : (const LT*)(P.vol + h.pal_off);
+    const bool vec = ((uintptr_t)out & (4 * sizeof(LT) - 1)) == 0;
+    if (t <= 4) {
+        const V* g = st.full + fbase(t);
+        if (S < 4) {
+            const uint32_t n = S * S * S;
+            for (uint32_t v = threadIdx.x; v < n; v += NT) {
+                const uint32_t x = v & (S - 1), y = (v >> t) & (S - 1), z = v >> (2 * t);
+                out[v] = pal_get<LT, PAL_LDS>(pal, g[spread3(x) | (spread3(y) << 1) | (spread3(z) << 2)] & VIDX, pc);
+            }
+            return;
+        }
+        const uint32_t units = (S * S * S) >> 2;
+        for (uint32_t u = threadIdx.x; u < units; u += NT) {
+            const uint32_t lin = u << 2;
+            const uint32_t x = lin & (S - 1), y = (lin >> t) & (S - 1), z = lin >> (2 * t);
             const uint32_t m = spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
-            const uint64_t l = pal_read(P, h, sh.U, st.full[fbase(t) + m] & IDXV);
-            if (lb == 4) ((uint32_t*)out)[v] = (uint32_t)l;
-            else ((uint64_t*)out)[v] = l;
+            store4<LT>(out + lin, pal_get<LT, PAL_LDS>(pal, g[m] & VIDX, pc), pal_get<LT, PAL_LDS>(pal, g[m + 1] & VIDX, pc),
+                       pal_get<LT, PAL_LDS>(pal, g[m + 8] & VIDX, pc), pal_get<LT, PAL_LDS>(pal, g[m + 9] & VIDX, pc), vec);
         }
         return;
     }
     const uint32_t hb = t - 1, H = 1u << hb;  // parents per axis
-    const uint32_t n = H * H * H;
-    const bool vec = ((uintptr_t)out & (2 * lb - 1)) == 0;
-    for (uint32_t u = threadIdx.x; u < n; u += NT) {
-        const uint32_t qx = u & (H - 1), qy = (u >> hb) & (H - 1), qz = u >> (2 * hb);
-        const uint32_t q = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
-        const uint64_t e0 = ((uint64_t)(2 * qz) * S + 2 * qy) * S + 2 * qx;
-        uint64_t lab[8];
-        if (st.ebit(t - 1, q)) {
-            if (t <= 5) {
-                const uint32_t r = st.rank(t - 1, q);
+    const uint32_t units = (H >> 1) * H * H;   // pairs of parents along x
+    for (uint32_t u = threadIdx.x; u < units; u += NT) {
+        const uint32_t px = u & ((H >> 1) - 1), qy = (u >> (hb - 1)) & (H - 1), qz = u >> (2 * hb - 1);
+        const uint64_t e0 = ((uint64_t)(2 * qz) * S + 2 * qy) * S + 4 * px;
+        // palette indices of the 8 children of each of the two nodes (child c = x | y << 1 | z << 2)
+        uint32_t ix[2][8];
 #pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    lab[c] = pal_read(P, h, sh.U, st.get(t, 8 * r + c) & IDXV);
-            } else {
+        for (int hx = 0; hx < 2; ++hx) {
+            const uint32_t qx = 2 * px + hx;
+            const uint32_t q = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
+            if (t == 5) {
+                if (st.ebit(4, q)) {
+                    const V* c = st.c5 + 8 * st.rank(4, q);
 #pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    const uint64_t e = e0 + ((uint64_t)((c >> 2) & 1) * S + ((c >> 1) & 1)) * S + (c & 1);
-                    lab[c] = pal_read(P, h, sh.U, st.out6[e * st.lb4] & 0x7FFFFFFFu);
+                    for (int ch = 0; ch < 8; ++ch) ix[hx][ch] = c[ch] & VIDX;
+                } else {
+                    const uint32_t v = st.full[fbase(4) + q] & VIDX;
+#pragma unroll
+                    for (int ch = 0; ch < 8; ++ch) ix[hx][ch] = v;
                 }
-            }
-        } else {
-            const uint64_t l = pal_read(P, h, sh.U, st.value_at(t - 1, q) & IDXV);
+            } else if (st.ebit5(q)) {
+                const uint32_t* o6 = st.out6 + (e0 + 2 * hx) * st.lb4;
 #pragma unroll
-            for (int c = 0; c < 8; ++c) lab[c] = l;
+                for (int ch = 0; ch < 8; ++ch)
+                    ix[hx][ch] = o6[((((ch >> 2) & 1) * S + ((ch >> 1) & 1)) * S + (ch & 1)) * st.lb4] & 0x7FFFFFFFu;
+            } else {
+                const uint32_t v = st.value5(q) & VIDX;
+#pragma unroll
+                for (int ch = 0; ch < 8; ++ch) ix[hx][ch] = v;
+            }
         }
-        // child c = x | y << 1 | z << 2 of the block
 #pragma unroll
         for (int zy = 0; zy < 4; ++zy) {
-            const uint64_t e = e0 + ((uint64_t)(zy >> 1) * S + (zy & 1)) * S;
-            store_pair(out, lb, e, lab[2 * zy], lab[2 * zy + 1], vec);
+            store4<LT>(out + e0 + ((uint64_t)(zy >> 1) * S + (zy & 1)) * S,
+                       pal_get<LT, PAL_LDS>(pal, ix[0][2 * zy], pc), pal_get<LT, PAL_LDS>(pal, ix[0][2 * zy + 1], pc),
+                       pal_get<LT, PAL_LDS>(pal, ix[1][2 * zy], pc), pal_get<LT, PAL_LDS>(pal, ix[1][2 * zy + 1], pc), vec);
         }
+    }
+}
+
+template <int NT, typename V>
+__device__ __forceinline__ void write_output(const Params& P, Shared& sh, const Store<V>& st) {
+    if (P.label_bytes == 4) {
+        if (sh.h.pal_lds) write_labels<NT, V, uint32_t, true>(P, sh, st);
+        else write_labels<NT, V, uint32_t, false>(P, sh, st);
+    } else {
+        if (sh.h.pal_lds) write_labels<NT, V, uint64_t, true>(P, sh, st);
+        else write_labels<NT, V, uint64_t, false>(P, sh, st);
     }
 }
 
 // ------------------------------------------------------------------ a task
 template <int NT, typename V, bool BIG>
-__device__ void run_levels(const Params& P, Shared& sh, V* compact_lds, uint8_t* scratch, const uint8_t* nib) {
+__device__ __forceinline__ void run_levels(const Params& P, Shared& sh, uint16_t* slots_lds, uint8_t* scratch, const uint8_t* nib) {
     const TaskHdr& h = sh.h;
-    Store<V, BIG> st;
+    Store<V> st;
     st.E = sh.E;
     st.wpre = sh.wpre;
     st.E5 = (uint32_t*)(scratch + kScrE5);
     st.wpre5 = (uint16_t*)(scratch + kScrWpre5);
+    st.list_l = (uint16_t*)sh.U;
     st.list_g = (uint16_t*)(scratch + kScrList);
     st.pval_g = (uint32_t*)(scratch + kScrPval);
     st.lb4 = P.label_bytes / 4;
     st.out6 = (uint32_t*)(P.out + h.out_off * P.label_bytes);
     if (BIG) {
         st.full = (V*)(scratch + kScrFull);
-        st.c4 = (V*)(scratch + kScrComp);
-        st.c5 = st.c4 + 4096;
-        st.list_l = nullptr;
-        st.pval_l = nullptr;
+        st.c5 = (V*)(scratch + kScrComp);
     } else {
         st.full = (V*)sh.G;
-        st.c4 = compact_lds;
-        st.c5 = compact_lds + h.c5base;
-        st.list_l = (uint16_t*)sh.U;
-        st.pval_l = (V*)(sh.U + kUBytes / 2);
+        st.c5 = (V*)slots_lds;
     }
-    // parent lists: LDS on the fast path, except for 64^3 bricks at full
-    // resolution, whose level-6 parents (up to 32768) live in scratch
-    st.list_in_lds = !BIG && h.t <= 5;
-    decode_levels<NT, V, BIG>(P, sh, st, nib);
+    if (!BIG && h.t <= 5) decode_levels<NT, V, BIG, true>(P, sh, st, nib);
+    else decode_levels<NT, V, BIG, false>(P, sh, st, nib);
     if (sh.err) return;
-    // palette staging for the output pass (parent lists are no longer needed)
+    // palette staging for the output pass (the parent list is no longer needed)
     if (h.pal_lds) {
         const uint32_t words = (h.pc * P.label_bytes + 3) / 4;
         const uint32_t* src = (const uint32_t*)(P.vol + h.pal_off);
         for (uint32_t w = threadIdx.x; w < words; w += NT) ((uint32_t*)sh.U)[w] = src[w];
         __syncthreads();
     }
-    write_output<NT, V, BIG>(P, sh, st);
+    write_output<NT, V>(P, sh, st);
 }
 
 template <int NT>
-__device__ void decode_task(const Params& P, Shared& sh, uint16_t* compact_lds, uint8_t* scratch) {
+__device__ __forceinline__ void decode_task(const Params& P, Shared& sh, uint16_t* slots_lds, uint8_t* scratch) {
     const TaskHdr& h = sh.h;
     if (h.status != kTaskOk) {
         if (h.status == kTaskCorrupt && h.write_ok) zero_output<NT>(P, h);
@@ -763,16 +784,18 @@ __device__ void decode_task(const Params& P, Shared& sh, uint16_t* compact_lds, 
     if (h.coder == kRaw4) {
         nib = P.vol + h.pay_off;
     } else {
+        // the rANS table borrows the slot area (at least 16 KiB) until the levels start
+        uint32_t* tab = (uint32_t*)slots_lds;
         const uint4* src = (const uint4*)P.rans_tab;
-        for (uint32_t w = threadIdx.x; w < kRansM / 4; w += NT) ((uint4*)sh.U)[w] = src[w];
+        for (uint32_t w = threadIdx.x; w < kRansM / 4; w += NT) ((uint4*)tab)[w] = src[w];
         __syncthreads();
-        rans_decode<NT>(P, sh, scratch + kScrSym);
+        rans_decode<NT>(P, sh, tab, scratch + kScrSym);
         nib = scratch + kScrSym;
         __syncthreads();
     }
     if (!sh.err) {
-        if (h.big) run_levels<NT, uint32_t, true>(P, sh, nullptr, scratch, nib);
-        else run_levels<NT, uint16_t, false>(P, sh, compact_lds, scratch, nib);
+        if (h.big) run_levels<NT, uint32_t, true>(P, sh, slots_lds, scratch, nib);
+        else run_levels<NT, uint16_t, false>(P, sh, slots_lds, scratch, nib);
     }
     __syncthreads();
     if (sh.err) {
@@ -781,11 +804,12 @@ __device__ void decode_task(const Params& P, Shared& sh, uint16_t* compact_lds, 
     }
 }
 
+// at least 4 waves per SIMD: 128 VGPRs per lane at most
 template <int NT>
-__global__ void __launch_bounds__(NT) decode_kernel(Params P) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) decode_kernel(Params P) {
     extern __shared__ uint8_t dyn_smem[];
     Shared& sh = *reinterpret_cast<Shared*>(dyn_smem);
-    uint16_t* compact_lds = reinterpret_cast<uint16_t*>(dyn_smem + sizeof(Shared));
+    uint16_t* slots_lds = reinterpret_cast<uint16_t*>(dyn_smem + sizeof(Shared));
     const uint32_t tid = threadIdx.x;
     uint8_t* scratch = P.scratch + (uint64_t)blockIdx.x * P.scratch_stride;
     uint32_t iter = 0;
@@ -805,7 +829,7 @@ __global__ void __launch_bounds__(NT) decode_kernel(Params P) {
         ++iter;
         const uint32_t task = sh.h.task;
         if (task == 0xFFFFFFFFu) break;
-        decode_task<NT>(P, sh, compact_lds, scratch);
+        decode_task<NT>(P, sh, slots_lds, scratch);
         __syncthreads();
         if (tid == 0 && P.status) P.status[task] = sh.h.status;
         __syncthreads();
@@ -923,7 +947,7 @@ __global__ void __launch_bounds__(1024) dense_offsets_kernel(Params P, uint64_t*
 }
 
 // ------------------------------------------------------------ host launch
-size_t shared_bytes(uint32_t cap16) { return sizeof(Shared) + 2ull * cap16; }
+size_t shared_bytes(uint32_t cap16) { return sizeof(Shared) + 2ull * (cap16 < kMinCap16 ? kMinCap16 : cap16); }
 
 template <int NT>
 static hipError_t launch_nt(const Params& P, uint32_t grid, hipStream_t s) {
@@ -941,6 +965,24 @@ hipError_t set_kernel_attrs() {
     if ((e = hipFuncSetAttribute((const void*)decode_kernel<512>, hipFuncAttributeMaxDynamicSharedMemorySize, maxb)))
         return e;
     return hipFuncSetAttribute((const void*)decode_kernel<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, maxb);
+}
+
+template <int NT>
+static int resident_nt(uint32_t cap16) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, decode_kernel<NT>, NT, shared_bytes(cap16)) != hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
+}
+
+int max_resident_per_cu(int wg_size, uint32_t cap16) {
+    switch (wg_size) {
+    case 128: return resident_nt<128>(cap16);
+    case 256: return resident_nt<256>(cap16);
+    case 512: return resident_nt<512>(cap16);
+    case 1024: return resident_nt<1024>(cap16);
+    default: return 1;
+    }
 }
 
 hipError_t launch_decode(const Params& P, int wg_size, uint32_t grid, hipStream_t s) {

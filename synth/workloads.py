@@ -57,3 +57,52 @@ def uneven1024(seed: int = 0, tiles_side: int = 16):
     origins = np.array([o for o, _ in lay], dtype=np.uint32)
     flat, _, kinds = uneven_batch_u64(l2, seed)
     return flat, l2, origins, kinds
+
+
+def frustum_requests(n_requests: int, grid, rate_hz: float, brick: int = 32, seed: int = 0, fov_deg: float = 60.0,
+                     screen_h: int = 1080, max_lod: int = 4, orbit=(0.75, 8.0), n_max: int = 4096):
+    """A Poisson stream of brick-set requests from random orbiting camera frusta.
+
+    Request i arrives at the i-th event of a Poisson process of rate rate_hz.
+    Its camera sits at distance U[orbit] x (volume extent) from the volume
+    centre in a uniformly random direction and looks at the centre; the
+    visible bricks are those whose centre lies within half the field of view
+    of the view direction.  A brick at distance d gets LOD
+    clamp(floor(log2(2 d tan(fov/2) / screen_h)), 0, max_lod), i.e. about one
+    voxel per pixel.  The request is n ~ log-uniform[1, n_max] bricks drawn
+    without replacement from the visible ones.
+
+    Returns (ids u32, lods u8, starts u64[n+1], arrivals f64[n] in seconds).
+    """
+    rng = np.random.default_rng(seed + 7001)
+    nbx, nby, nbz = grid
+    extent = float(brick * max(grid))
+    g = np.stack(np.meshgrid(np.arange(nbx), np.arange(nby), np.arange(nbz), indexing="ij"), -1).reshape(-1, 3)
+    bid = (g[:, 0] + nbx * (g[:, 1] + nby * g[:, 2])).astype(np.uint32)
+    centres = ((g.astype(np.float64) + 0.5) * brick).astype(np.float32)
+    cc = (centres.astype(np.float64) ** 2).sum(1)
+    vol_c = np.array([nbx, nby, nbz], np.float64) * brick * 0.5
+    half = np.deg2rad(fov_deg) / 2
+    cos_half = np.cos(half)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate_hz, size=n_requests))
+    ids, lods, starts = [], [], [0]
+    for _ in range(n_requests):
+        v = rng.normal(size=3)
+        v /= np.linalg.norm(v)
+        cam = vol_c + v * (extent * rng.uniform(*orbit))
+        # centre . (-v) and centre . cam for every brick in one product
+        dots = centres @ np.stack([-v, cam], 1).astype(np.float32)
+        dist = np.sqrt(np.maximum(cc - 2.0 * dots[:, 1] + cam @ cam, 0.0))
+        along = dots[:, 0] + cam @ v  # (centre - cam) . (-v)
+        vis = np.nonzero(along >= cos_half * dist)[0]
+        n = int(round(np.exp(rng.uniform(0.0, np.log(n_max)))))
+        if len(vis) == 0:
+            vis = np.array([int(np.argmin(dist))])
+        n = max(1, min(n, len(vis)))
+        pick = rng.choice(vis, size=n, replace=False)
+        lod = np.floor(np.log2(np.maximum(2 * dist[pick] * np.tan(half) / screen_h, 1e-9)))
+        ids.append(bid[pick])
+        lods.append(np.clip(lod, 0, max_lod).astype(np.uint8))
+        starts.append(starts[-1] + n)
+    return (np.concatenate(ids).astype(np.uint32), np.concatenate(lods).astype(np.uint8),
+            np.array(starts, dtype=np.uint64), arrivals)
