@@ -294,10 +294,35 @@ def _dense(wl, sel):
 
 # ------------------------------------------------------------ profile summary
 def summarize_rocprof(directory: str, workload: str) -> str:
-    """Text summary of a rocprofv3 run of this script: kernel-trace statistics
-    and/or per-kernel counter means (FETCH_SIZE, WRITE_SIZE, ...)."""
+    """Text summary of a rocprofv3 run of this script (its SQLite output, or
+    CSV): kernel-trace statistics and/or per-kernel counter means."""
     import csv
+    import sqlite3
     lines = ["workload: %s" % workload, "kernel_source_sha256_16: %s" % kernel_source_hash()]
+    for path in sorted(glob.glob(os.path.join(directory, "**", "*_results.db"), recursive=True)):
+        con = sqlite3.connect(path)
+        try:
+            rows = con.execute("select name, total_calls, average, total_duration, percentage from top_kernels "
+                               "order by total_duration desc limit 12").fetchall()
+            if rows:
+                # the top_kernels view reports microseconds
+                lines.append("# kernel trace (%s), durations in ns" % os.path.basename(path))
+                for name, calls, avg, tot, pct in rows:
+                    lines.append("%-64s calls %5d  avg_ns %12.1f  total_ns %14.1f  pct %5.1f" % (
+                        name[:64], calls, 1e3 * avg, 1e3 * tot, pct))
+        except sqlite3.Error:
+            pass
+        try:
+            rows = con.execute("select kernel_name, counter_name, count(*), avg(value) from counters_collection "
+                               "group by kernel_name, counter_name").fetchall()
+            if rows:
+                lines.append("# counters (%s): mean per dispatch" % os.path.basename(path))
+                for name, ctr, n, mean in sorted(rows, key=lambda r: (DECODE_KERNEL not in r[0], r[0], r[1])):
+                    kind = "decode_kernel" if DECODE_KERNEL in name else name.split("(")[0][-40:]
+                    lines.append("%-40s %-24s dispatches %4d  mean %.6g" % (kind, ctr, n, mean))
+        except sqlite3.Error:
+            pass
+        con.close()
     for path in sorted(glob.glob(os.path.join(directory, "**", "*kernel_stats.csv"), recursive=True)):
         lines.append("# %s" % os.path.relpath(path, directory))
         with open(path) as f:
@@ -305,17 +330,6 @@ def summarize_rocprof(directory: str, workload: str) -> str:
                 lines.append("%-60s calls %6s  avg_ns %12s  total_ns %14s  pct %s" % (
                     row.get("Name", "")[:60], row.get("Calls"), row.get("AverageNs"), row.get("TotalDurationNs"),
                     row.get("Percentage")))
-    for path in sorted(glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)):
-        sums = {}
-        with open(path) as f:
-            for row in csv.DictReader(f):
-                name = row.get("Kernel_Name", "")
-                kind = "decode" if DECODE_KERNEL in name else name.split("(")[0][-48:]
-                sums.setdefault((kind, row.get("Counter_Name")), []).append(float(row.get("Counter_Value", 0) or 0))
-        lines.append("# %s" % os.path.relpath(path, directory))
-        for (kind, ctr), vals in sorted(sums.items()):
-            lines.append("%-50s %-18s dispatches %4d  mean %.6g  min %.6g  max %.6g" % (
-                kind, ctr, len(vals), float(np.mean(vals)), float(np.min(vals)), float(np.max(vals))))
     return "\n".join(lines) + "\n"
 
 

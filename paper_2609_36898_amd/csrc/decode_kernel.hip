@@ -73,6 +73,7 @@ struct Shared {
     TaskHdr h;
     uint32_t err;
     uint32_t pub[2][kMaxWaves];
+    uint32_t head[2][kMaxWaves];         // first 8 symbols of each wave's share of a pass
     uint32_t red[kMaxWaves + 2];
     uint32_t E[kEWords];                 // expansion bitmaps of levels 0..4
     uint16_t wpre[kEWords];              // exclusive popcount prefix of each bitmap word
@@ -133,6 +134,43 @@ __device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t* total, 
 // (state 0: the next symbol is an operation; state 1: it is a delta entry).
 __device__ __forceinline__ uint32_t fn_then(uint32_t first, uint32_t second) {
     return ((second >> (first & 1u)) & 1u) | (((second >> ((first >> 1) & 1u)) & 1u) << 1);
+}
+
+// DPP moves (GFX9 controls).  A lane whose source lane does not exist, or
+// whose row is masked off, keeps `old`.
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ uint32_t dpp(uint32_t old, uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROWS, 0xF, false);
+}
+constexpr int kDppRowShr = 0x110;   // + n: lane l takes lane l - n of its row of 16
+constexpr int kDppWaveShl1 = 0x130;  // lane l takes lane l + 1
+constexpr int kDppWaveShr1 = 0x138;  // lane l takes lane l - 1
+constexpr int kDppBcast15 = 0x142;   // rows 1, 3 take lane 15 of the row before
+constexpr int kDppBcast31 = 0x143;   // rows 2, 3 take lane 31
+constexpr uint32_t kFnId = 2u;       // transfer function that keeps the state
+
+// Inclusive scan of 2-state transfer functions over the wavefront (lane 0
+// first): Hillis-Steele within rows of 16, then across rows by broadcasts.
+__device__ __forceinline__ uint32_t wave_scan_fn(uint32_t f) {
+    f = fn_then(dpp<kDppRowShr + 1>(kFnId, f), f);
+    f = fn_then(dpp<kDppRowShr + 2>(kFnId, f), f);
+    f = fn_then(dpp<kDppRowShr + 4>(kFnId, f), f);
+    f = fn_then(dpp<kDppRowShr + 8>(kFnId, f), f);
+    f = fn_then(dpp<kDppBcast15, 0xA>(kFnId, f), f);
+    f = fn_then(dpp<kDppBcast31, 0xC>(kFnId, f), f);
+    return f;
+}
+
+// The 4-bit symbols of this lane and the next seven lanes, low nibble first
+// (0 past lane 63).
+__device__ __forceinline__ uint32_t next8(uint32_t s) {
+    uint32_t r = s, v = s;
+#pragma unroll
+    for (int m = 1; m < 8; ++m) {
+        v = dpp<kDppWaveShl1>(0u, v);
+        r |= v << (4 * m);
+    }
+    return r;
 }
 
 // -------------------------------------------------------------- palette
@@ -425,11 +463,15 @@ __device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const 
     for (uint32_t c = s0; c < s1; c += NT) {
         const uint32_t j = c + tid;
         const bool valid = j < s1;
-        const uint32_t s = snext;
+        const uint32_t s = snext, pb = pbuf;
         if (j + NT < s1) {
             const uint32_t jn = j + NT;
             snext = (nib[jn >> 1] >> (4 * (jn & 1))) & 15u;
         }
+        // delta entries come from registers: this lane's symbol and the next seven of
+        // the wave; lanes near the wave's end complete them from the next wave's head
+        const uint32_t n8 = next8(s);
+        if (lane == 0) sh.head[pb][wave] = n8;
         // classification for both entry states
         const uint64_t m_valid = __ballot(valid);
         const uint64_t m_cand = __ballot(valid && (s & 7u) == kDelta);
@@ -451,22 +493,16 @@ __device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const 
             }
         } else {
             const uint32_t f = valid ? (((s & 7u) == kDelta ? 1u : 0u) | (((s >> 3) & 1u) << 1)) : 2u;
-            uint32_t incl = f;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const uint32_t o = __shfl_up(incl, d, 64);
-                if (lane >= (uint32_t)d) incl = fn_then(o, incl);
-            }
-            uint32_t excl = __shfl_up(incl, 1, 64);
-            if (lane == 0) excl = 2u;
+            const uint32_t incl = wave_scan_fn(f);
+            const uint32_t excl = dpp<kDppWaveShr1>(kFnId, incl);
             ops0 = __ballot(valid && !(excl & 1u));
             ops1 = __ballot(valid && !((excl >> 1) & 1u));
-            const uint32_t tot = __shfl(incl, 63, 64);
+            const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
             x0 = tot & 1u;
             x1 = (tot >> 1) & 1u;
         }
         if (lane == 0) {
-            sh.pub[pbuf][wave] = (uint32_t)__popcll(ops0) | ((uint32_t)__popcll(ops1) << 7) |
+            sh.pub[pb][wave] = (uint32_t)__popcll(ops0) | ((uint32_t)__popcll(ops1) << 7) |
                                  ((uint32_t)__popcll(ops0 & m_adv) << 14) | ((uint32_t)__popcll(ops1 & m_adv) << 21) |
                                  (x0 << 28) | (x1 << 29);
         }
@@ -480,7 +516,7 @@ __device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const 
                 my_kb = kb;
                 my_ab = ab;
             }
-            const uint32_t p = sh.pub[pbuf][w];
+            const uint32_t p = sh.pub[pb][w];
             const uint32_t q = e ? (p >> 7) : p;
             kb += q & 127u;
             ab += (q >> 14) & 127u;
@@ -541,15 +577,23 @@ __device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const 
                     if (a == 0) bad = true;
                     else v = FIN | (a - 1u);
                 } else if (op == kDelta) {
-                    uint32_t d = 0, jj = j + 1, en = 8;
+                    // entries j+1 .. j+lim-1 are in w8; later ones (past the pass) are read
+                    uint32_t w8 = n8, lim = 8;
+                    if (lane > 56u) {
+                        const uint32_t sft = 4u * (64u - lane);
+                        if (wave + 1 < NW) w8 = (w8 & ((1u << sft) - 1u)) | (sh.head[pb][wave + 1] << sft);
+                        else lim = 64u - lane;
+                    }
+                    uint32_t d = 0, m = 1, en = 8;
                     while (en & 8u) {
+                        const uint32_t jj = j + m;
                         if (jj >= s1) {
                             bad = true;
                             break;
                         }
-                        en = (nib[jj >> 1] >> (4 * (jj & 1))) & 15u;
+                        en = m < lim ? (w8 >> (4 * m)) & 15u : (nib[jj >> 1] >> (4 * (jj & 1))) & 15u;
                         d = d >= (1u << 29) ? 0xFFFFFFFFu : ((d << 3) | (en & 7u));
-                        ++jj;
+                        ++m;
                     }
                     if (d == 0 || d > a) bad = true;
                     else v = FIN | (a - d);
@@ -873,16 +917,42 @@ __device__ __forceinline__ uint32_t task_t(const Params& P, uint32_t j, uint64_t
     return L - lod;
 }
 
-// task cost classes for a decreasing-cost pop order: cls = 63 - clz(cost)
-__global__ void cost_class_kernel(Params P, uint32_t* cls, uint32_t* hist) {
-    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= P.n_tasks) return;
-    uint64_t rec;
-    const uint32_t t = task_t(P, j, &rec);
-    const uint64_t cost = rec + (t <= kMaxLog2b ? ((uint64_t)1 << (3 * t)) * P.label_bytes : 0) + 1;
-    const uint32_t c = 63u - (uint32_t)__clzll(cost);
-    cls[j] = c;
-    atomicAdd(&hist[c], 1u);
+// Lanes of one wavefront grouped by class: for every distinct class c among
+// the lanes with c < 64, f(c, mask of the lanes holding it) runs once, with
+// the lowest such lane as the leader.  One atomic per (wavefront, class)
+// instead of one per task keeps the cost sort free of same-address contention.
+template <typename F>
+__device__ __forceinline__ void for_each_class(uint32_t c, F f) {
+    uint64_t left = __ballot(c < 64u);
+    while (left) {
+        const uint32_t lead = (uint32_t)__builtin_ctzll(left);
+        const uint32_t cc = (uint32_t)__builtin_amdgcn_readlane((int)c, (int)lead);
+        const uint64_t m = __ballot(c == cc);
+        f(cc, m, lead);
+        left &= ~m;
+    }
+}
+
+// Task cost classes for a decreasing-cost pop order: the class of a task is
+// floor(log2(record bytes + output bytes + 1)); also the class histogram.  256 threads per block.
+__global__ void __launch_bounds__(256) cost_class_kernel(Params P, uint32_t* cls, uint32_t* hist) {
+    __shared__ uint32_t cnt[64];
+    const uint32_t tid = threadIdx.x, j = blockIdx.x * 256 + tid, lane = lane_id();
+    if (tid < 64) cnt[tid] = 0;
+    __syncthreads();
+    uint32_t c = 64;
+    if (j < P.n_tasks) {
+        uint64_t rec;
+        const uint32_t t = task_t(P, j, &rec);
+        const uint64_t cost = rec + (t <= kMaxLog2b ? ((uint64_t)1 << (3 * t)) * P.label_bytes : 0) + 1;
+        c = 63u - (uint32_t)__clzll(cost);
+        cls[j] = c;
+    }
+    for_each_class(c, [&](uint32_t cc, uint64_t m, uint32_t lead) {
+        if (lane == lead) atomicAdd(&cnt[cc], (uint32_t)__popcll(m));
+    });
+    __syncthreads();
+    if (tid < 64 && cnt[tid]) atomicAdd(&hist[tid], cnt[tid]);
 }
 
 // exclusive scan of the 64-bin histogram in decreasing class order (one wave)
@@ -898,10 +968,32 @@ __global__ void cost_scan_kernel(uint32_t* hist, uint32_t* cursor) {
     cursor[c] = incl - v;
 }
 
-__global__ void cost_scatter_kernel(uint32_t n, const uint32_t* cls, uint32_t* cursor, uint32_t* order) {
-    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    order[atomicAdd(&cursor[cls[j]], 1u)] = j;
+// Scatter task indices to their class's range of the order: a block reserves
+// one range per class it holds, and ranks its lanes within it by wavefront
+// and lane.  256 threads per block.
+__global__ void __launch_bounds__(256) cost_scatter_kernel(uint32_t n, const uint32_t* cls, uint32_t* cursor, uint32_t* order) {
+    __shared__ uint32_t cnt[4][64];
+    __shared__ uint32_t base[64];
+    const uint32_t tid = threadIdx.x, j = blockIdx.x * 256 + tid, lane = lane_id(), wave = tid >> 6;
+    cnt[wave][lane] = 0;
+    __syncthreads();
+    const uint32_t c = j < n ? cls[j] : 64u;
+    uint32_t rank = 0;
+    for_each_class(c, [&](uint32_t cc, uint64_t m, uint32_t lead) {
+        if (c == cc) rank = mbcnt(m);
+        if (lane == lead) cnt[wave][cc] = (uint32_t)__popcll(m);
+    });
+    __syncthreads();
+    if (tid < 64) {
+        const uint32_t tot = cnt[0][tid] + cnt[1][tid] + cnt[2][tid] + cnt[3][tid];
+        base[tid] = tot ? atomicAdd(&cursor[tid], tot) : 0u;
+    }
+    __syncthreads();
+    if (j < n) {
+        uint32_t pos = base[c] + rank;
+        for (uint32_t w = 0; w < wave; ++w) pos += cnt[w][c];
+        order[pos] = j;
+    }
 }
 
 __global__ void zero_u32_kernel(uint32_t* p, uint32_t n) {
