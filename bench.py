@@ -216,7 +216,7 @@ def measure(wl: Workload, args, dev):
     }
 
     if args.calib_copy:
-        src = torch.empty(1 << 28, dtype=torch.int32, device=dev)
+        src = torch.empty(CALIB_COPY_BYTES // 4, dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
@@ -333,6 +333,49 @@ def summarize_rocprof(directory: str, workload: str) -> str:
     return "\n".join(lines) + "\n"
 
 
+CALIB_COPY_BYTES = 1 << 30  # --calib-copy moves this many bytes per copy
+
+
+def _counter_values(directory: str, counter: str):
+    """Per-dispatch values of one counter: {kernel kind: [values]} from rocprofv3's SQLite output."""
+    import sqlite3
+    vals = {}
+    for path in sorted(glob.glob(os.path.join(directory, "**", "*_results.db"), recursive=True)):
+        con = sqlite3.connect(path)
+        for name, v in con.execute("select kernel_name, value from counters_collection where counter_name = ?",
+                                   (counter,)):
+            kind = DECODE_KERNEL if DECODE_KERNEL in name else name.split("(")[0].split()[-1]
+            vals.setdefault(kind, []).append(float(v))
+        con.close()
+    return vals
+
+
+def summarize_traffic(fetch_dir: str, write_dir: str, workload: str) -> str:
+    """HBM bytes per decode launch from FETCH_SIZE and WRITE_SIZE runs (KiB per
+    dispatch), each scaled by what the same counter reads for the calibration
+    copy of CALIB_COPY_BYTES."""
+    f = _counter_values(fetch_dir, "FETCH_SIZE")
+    w = _counter_values(write_dir, "WRITE_SIZE")
+    copy_f = max(f.get("__amd_rocclr_copyBuffer", [0.0]))
+    copy_w = max(w.get("__amd_rocclr_copyBuffer", [0.0]))
+    if not f.get(DECODE_KERNEL) or not w.get(DECODE_KERNEL) or copy_f <= 0 or copy_w <= 0:
+        raise SystemExit("need decode and calibration-copy dispatches in both runs")
+    kf = CALIB_COPY_BYTES / 1024.0 / copy_f
+    kw = CALIB_COPY_BYTES / 1024.0 / copy_w
+    df, dw = float(np.mean(f[DECODE_KERNEL])), float(np.mean(w[DECODE_KERNEL]))
+    rd, wr = df * kf * 1024.0, dw * kw * 1024.0
+    return "\n".join([
+        "workload: %s" % workload,
+        "kernel_source_sha256_16: %s" % kernel_source_hash(),
+        "calibration copy of %d bytes: FETCH_SIZE %.1f KiB (scale %.4f), WRITE_SIZE %.1f KiB (scale %.4f)" % (
+            CALIB_COPY_BYTES, copy_f, kf, copy_w, kw),
+        "decode_kernel dispatches: FETCH_SIZE %d, WRITE_SIZE %d" % (len(f[DECODE_KERNEL]), len(w[DECODE_KERNEL])),
+        "decode_kernel FETCH_SIZE mean %.1f KiB -> read bytes %.0f" % (df, rd),
+        "decode_kernel WRITE_SIZE mean %.1f KiB -> written bytes %.0f" % (dw, wr),
+        "hbm_bytes_per_launch: %.0f" % (rd + wr),
+    ]) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -346,9 +389,13 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="default launch shape instead of the autotuner")
     ap.add_argument("--tune-cache", default=os.environ.get("CSGV_TUNE_CACHE", "/tmp/csgv_autotune.txt"))
     ap.add_argument("--calib-copy", action="store_true",
-                    help="also run a 1 GiB device-to-device copy (reference kernel for HBM counter scaling)")
+                    help="also run device-to-device copies of CALIB_COPY_BYTES (reference kernel for HBM counter scaling)")
     ap.add_argument("--summarize-rocprof", default=None, metavar="DIR")
+    ap.add_argument("--summarize-traffic", nargs=2, default=None, metavar=("FETCH_DIR", "WRITE_DIR"))
     args = ap.parse_args()
+    if args.summarize_traffic:
+        sys.stdout.write(summarize_traffic(*args.summarize_traffic, (args.workload or [HEADLINE])[0]))
+        return
     if args.summarize_rocprof:
         sys.stdout.write(summarize_rocprof(args.summarize_rocprof, (args.workload or [HEADLINE])[0]))
         return
