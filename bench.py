@@ -1,19 +1,24 @@
 """Benchmark of the CSGV brick decoder on one MI355X.
 
-Prints ONE JSON line.  The headline is the largest single-GPU batched
-workload: a 1024^3 u32 neurite volume (100,000 spline tubes), 32,768 bricks of
-32^3 at per-brick LOD uniform in {0..3}, decoded in one autotuned persistent
-launch (graph-captured plan).  Secondary entries: the 512^3 Voronoi volume with
-voids (4096 bricks, LOD 0), the 1024^3 u64 uneven batch (18,600 bricks of 32^3
-and 64^3, batched vs plain) and the 128^3 Voronoi volume (plain).
+Prints ONE JSON line.  The headline is the largest workload, the served one:
+a 2048^3 u32 neurite volume (800,000 spline tubes, 262,144 bricks of 32^3)
+resident compressed in HBM with a 24 GiB decoded-brick cache, fed a stream of
+frustum brick-set requests (1..4096 bricks, LOD 0..4).  It reports decoded
+GVoxel/s at saturation (a step = one request of the measured trace) and p50 /
+p99 request latency at 0.5x and 0.8x the saturation request rate.  Secondary
+entries: the 1024^3 neurite volume (32,768 bricks at per-brick LOD 0..3, one
+autotuned persistent launch), the 512^3 Voronoi volume with voids (4096
+bricks, LOD 0), the 1024^3 u64 uneven batch (32^3 and 64^3 bricks, batched vs
+plain) and the 128^3 Voronoi volume (plain).
 
-Every entry: decoded GVoxel/s over whole steps (inputs resident in HBM before
-the timed region), the decode kernel's HBM roofline fraction from HIP events
-on the plan's launch stream, bit-exactness of the timed output, and the CPU
-oracle (all host cores, and one thread on a sample) decoding the same tasks.
+Every entry: decoded GVoxel/s with inputs resident in HBM before the timed
+region, the decode kernel's HBM roofline fraction from HIP events on the
+stream it runs on, bit-exactness against the CPU oracle, and the oracle timed
+on the host cores over the same tasks (or a bounded sample of them).
 
     python bench.py [--steps K] [--warmup W] [--workload NAME ...] [--no-cpu] [--no-plain]
     python bench.py --summarize-rocprof DIR --workload NAME   (profile summary text)
+    python bench.py --summarize-traffic FETCH_DIR WRITE_DIR --workload NAME
 """
 from __future__ import annotations
 
@@ -34,8 +39,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-HEADLINE = "neurite1024"
-SECONDARY = ["voronoi512", "uneven1024", "voronoi128"]
+HEADLINE = "neurite2048"
+SECONDARY = ["neurite1024", "voronoi512", "uneven1024", "voronoi128"]
+SERVE_CACHE_BYTES = 24 << 30  # decoded brick cache of the served workload
+SERVE_SIDE, SERVE_SLAB = 2048, 32
 DECODE_KERNEL = "decode_kernel"
 
 
@@ -100,6 +107,7 @@ class Workload:
         self.raw_lod0 = raw_lod0  # expected output when every task is LOD 0 in brick order
         self.config = config or {}
         self.plain = plain
+        self.served = False
 
 
 def build_workload(name: str) -> Workload:
@@ -138,6 +146,22 @@ def build_workload(name: str) -> Workload:
                        "kinds": {"constant": int((kinds == 0).sum()), "voronoi": int((kinds == 1).sum()),
                                  "noise": int((kinds == 2).sum())},
                        "form": "persistent+graph vs plain"}, plain=True)
+    elif name == "neurite2048":
+        # generated and encoded slab by slab (32 planes = one layer of bricks)
+        n = SERVE_SIDE
+        enc = P.csgv.csgv_encoder(4, dims=(n, n, n))
+        for z0 in range(0, n, SERVE_SLAB):
+            b = P.bricks_of_volume(W.neurite2048_slab(z0, z0 + SERVE_SLAB), 5)
+            enc.add(b, np.full(len(b) >> 15, 5, np.uint8))
+            del b
+        c = enc.finish()
+        nb = (n // 32) ** 3
+        wl = Workload(name, c, np.zeros(0), np.zeros(0), 4, None,
+                      {"workload": "neurite2048_u32_b32_served", "volume": [n] * 3, "bricks": nb,
+                       "tubes": W.NEURITE2048_TUBES, "cache_bytes": SERVE_CACHE_BYTES,
+                       "requests": "Poisson arrivals of frustum brick sets, n log-uniform in [1, 4096], LOD 0..4",
+                       "form": "served: LRU brick cache + continuous batching"})
+        wl.served = True
     else:
         raise ValueError("unknown workload " + name)
     wl.config["compressed_bytes"] = len(c)
@@ -252,6 +276,145 @@ def measure(wl: Workload, args, dev):
     del out, status, dv
     torch.cuda.empty_cache()
     return res
+
+
+def measure_served(wl: Workload, args, dev):
+    """The served workload: the compressed volume and a 24 GiB decoded-brick
+    cache resident in HBM, a stream of frustum requests through the server.
+
+    Three runs on fresh servers, each after the same warm-up requests: every
+    measured request at t = 0 (saturation: the admission queue never empties),
+    then Poisson arrivals at 0.5x and 0.8x the saturation request rate.  A
+    request's latency runs from its arrival until all of its pairs are
+    resident.  GVoxel/s counts voxels decoded (cache misses) per second of the
+    run; served GVoxel/s counts every requested voxel.  Bit-exactness: pinned
+    requests of the trace, served one by one, against the CPU oracle."""
+    import torch
+    import oracle
+    import paper_2609_36898_amd as P
+    from synth import workloads as W
+    dv = P.DeviceVolume(wl.container, device=dev)
+    cache_elems = SERVE_CACHE_BYTES // 4
+    cache = torch.empty(cache_elems, dtype=torch.int32, device=dev)
+    nw, nm = args.serve_warmup, args.serve_requests
+    g = SERVE_SIDE // 32
+    t0 = time.time()
+    ids, lods, starts, unit_arr = W.frustum_requests(nw + nm, (g, g, g), 1.0, seed=11, n_max=4096)
+    _log("%s: %d requests (%d pairs) generated in %.1f s" % (wl.name, nw + nm, len(ids), time.time() - t0))
+    sw = int(starts[nw])
+    m_ids, m_lods = ids[sw:], lods[sw:]
+    m_starts = starts[nw:] - starts[nw]
+    lod_hist = np.bincount(lods, minlength=5).tolist()
+
+    def run(rate):
+        srv = P.csgv.csgv_server(dv.info, dv.tensor, cache, cache_elems, n_streams=args.serve_streams,
+                                 max_batch=args.serve_batch)
+        srv.run(ids[:sw], lods[:sw], starts[:nw + 1], np.zeros(nw))
+        s0 = srv.stats()
+        arr = np.zeros(nm) if rate is None else (unit_arr[nw:] - unit_arr[nw]) / rate
+        rec = srv.run(m_ids, m_lods, m_starts, arr)
+        s1 = srv.stats()
+        srv.destroy()
+        d = {k: s1[k] - s0[k] for k in s1 if k not in ("cache_top", "resident", "pinned", "max_batch_seen")}
+        span = float(rec["t_done"].max())
+        lat = (rec["t_done"] - rec["t_arrival"]) * 1e3
+        ok = bool((rec["status"] == 0).all()) and d["failed_tasks"] == 0
+        res = {"rate_hz": None if rate is None else round(rate, 2), "requests": nm, "seconds": round(span, 4),
+               "requests_per_s": round(nm / span, 2),
+               "decoded_gvoxel_s": round(d["decoded_elements"] / span / 1e9, 3),
+               "served_gvoxel_s": round(d["requested_elements"] / span / 1e9, 3),
+               "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+               "hit_fraction": round((d["hits"] + d["joined"]) / max(d["pairs_requested"], 1), 4),
+               "batches": d["batches"], "decoded_pairs": d["decoded"], "evictions": d["evictions"],
+               "splits": d["splits"], "resets": d["resets"], "kernel_ms": round(d["kernel_ms"], 3), "all_ok": ok}
+        return res, d
+
+    sat, sat_d = run(None)
+    _log("%s: saturation %.0f req/s, %.2f GVoxel/s decoded, p50 %.2f ms" % (
+        wl.name, sat["requests_per_s"], sat["decoded_gvoxel_s"], sat["p50_ms"]))
+    loads = {}
+    for f in (0.5, 0.8):
+        loads["load_%.1f" % f], _ = run(f * sat["requests_per_s"])
+        _log("%s: %.1fx load: p50 %.3f ms p99 %.3f ms" % (wl.name, f, loads["load_%.1f" % f]["p50_ms"],
+                                                           loads["load_%.1f" % f]["p99_ms"]))
+    # the decode kernel over the saturation run: algorithmic bytes / kernel time
+    alg = sat_d["record_bytes"] + 4.0 * sat_d["decoded_elements"]
+    kgbs = alg / (sat_d["kernel_ms"] * 1e-3) / 1e9 if sat_d["kernel_ms"] > 0 else 0.0
+
+    # bit-exactness: pinned requests of the measured trace against the oracle
+    n_req = len(m_starts) - 1
+    sizes = np.diff(m_starts.astype(np.int64))
+    check = [r for r in range(n_req) if sizes[r] <= 1024][:args.serve_check]
+    srv = P.csgv.csgv_server(dv.info, dv.tensor, cache, cache_elems, n_streams=args.serve_streams,
+                             max_batch=args.serve_batch, keep_pinned=True)
+    exact = True
+    c_ids, c_lods, c_got = [], [], []
+    for r in check:
+        a, b = int(m_starts[r]), int(m_starts[r + 1])
+        rid, rl = m_ids[a:b], m_lods[a:b]
+        q = srv.submit(rid, rl, srv.clock())
+        done = []
+        while not done:
+            srv.step()
+            done = srv.drain()
+        exact &= all(d.status == 0 for d in done)
+        torch.cuda.synchronize()
+        for i, l in zip(rid, rl):
+            o = srv.where(int(i), int(l))
+            c_got.append(cache[o:o + (32 >> int(l)) ** 3].cpu().numpy().view(np.uint32))
+        c_ids.append(rid)
+        c_lods.append(rl)
+        srv.release(q)
+    srv.destroy()
+    c_ids, c_lods = np.concatenate(c_ids), np.concatenate(c_lods)
+    offs, total = P.dense_offsets(np.full(len(c_ids), 5, np.uint8), c_lods)
+    want, wst = oracle.decode_tasks(wl.container, c_ids, c_lods, offs, total, 4, nthreads=cpu_threads())
+    exact = exact and bool((wst == 0).all()) and bool(np.array_equal(np.concatenate(c_got), want))
+    _log("%s: %d pinned requests (%d pairs) bit-exact vs oracle: %s" % (wl.name, len(check), len(c_ids), exact))
+    del cache, dv
+    torch.cuda.empty_cache()
+
+    res = {
+        "value": sat["decoded_gvoxel_s"], "ms_per_step": round(1e3 * sat["seconds"] / nm, 4),
+        "config": dict(wl.config, warmup_requests=nw, measured_requests=nm, lod_histogram=lod_hist,
+                       streams=args.serve_streams, max_batch=args.serve_batch),
+        "roofline": {"bound": "hbm", "achieved": round(kgbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(kgbs / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(wl.name),
+                     "kernel": DECODE_KERNEL, "kernel_ms_total": round(sat_d["kernel_ms"], 3),
+                     "launches": sat_d["batches"], "alg_bytes_total": alg,
+                     "note": "over the saturation run: sum of algorithmic bytes / sum of decode-kernel times"},
+        "served": {"saturation": sat, **loads, "checked_requests": len(check), "checked_pairs": int(len(c_ids))},
+        "bit_exact": exact and sat["all_ok"] and all(v["all_ok"] for v in loads.values()),
+        "shape": {"wg_size": "default", "sort_tasks": "default"},
+        "autotune": None,
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline_served(wl, m_ids, m_lods, m_starts)
+    return res
+
+
+def cpu_baseline_served(wl: Workload, ids, lods, starts):
+    """The oracle decoding every pair of the first measured requests (about
+    1/20 of the trace's pairs, cache hits included) on all host cores."""
+    import oracle
+    import paper_2609_36898_amd as P
+    threads = cpu_threads()
+    k = int(np.searchsorted(starts.astype(np.int64), len(ids) // 20))
+    a = int(starts[k])
+    s_ids, s_lods = ids[:a], lods[:a]
+    offs, total = P.dense_offsets(np.full(len(s_ids), 5, np.uint8), s_lods)
+    out = np.empty(total, dtype=np.uint32)
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.decode_tasks(wl.container, s_ids, s_lods, offs, total, 4, nthreads=threads, out=out)
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
+    info = host_info()
+    return {"value": round(total / dt / 1e9, 4), "unit": "GVoxel/s", "cores": threads, "kind": "oracle",
+            "sample": "every pair of the first %d measured requests (%d pairs, %d voxels), OpenMP over pairs on "
+                      "%d threads, median of 3 runs of %.2f s" % (k, a, total, threads, dt),
+            "nproc": info["nproc"], "cpu_model": info["cpu_model"]}
 
 
 def cpu_baseline(wl: Workload, offs, total, gpu_out):
@@ -390,6 +553,11 @@ def main():
     ap.add_argument("--tune-cache", default=os.environ.get("CSGV_TUNE_CACHE", "/tmp/csgv_autotune.txt"))
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run device-to-device copies of CALIB_COPY_BYTES (reference kernel for HBM counter scaling)")
+    ap.add_argument("--serve-requests", type=int, default=10000, help="measured requests of the served workload")
+    ap.add_argument("--serve-warmup", type=int, default=1000, help="warm-up requests before each served run")
+    ap.add_argument("--serve-streams", type=int, default=3)
+    ap.add_argument("--serve-batch", type=int, default=4096)
+    ap.add_argument("--serve-check", type=int, default=24, help="pinned requests checked against the oracle")
     ap.add_argument("--summarize-rocprof", default=None, metavar="DIR")
     ap.add_argument("--summarize-traffic", nargs=2, default=None, metavar=("FETCH_DIR", "WRITE_DIR"))
     args = ap.parse_args()
@@ -412,19 +580,23 @@ def main():
     results = []
     for name in names:
         wl = build_workload(name)
-        r = measure(wl, args, dev)
-        _log("%s: %.2f GVoxel/s, kernel %.3f ms, roofline %.3f, bit_exact %s" % (
-            name, r["value"], r["roofline"]["kernel_ms"], r["roofline"]["frac"], r["bit_exact"]))
+        r = measure_served(wl, args, dev) if wl.served else measure(wl, args, dev)
+        _log("%s: %.2f GVoxel/s, roofline %.3f, bit_exact %s" % (
+            name, r["value"], r["roofline"]["frac"], r["bit_exact"]))
+        if "served" in r:
+            _log("%s: served %s" % (name, json.dumps(r["served"])))
         results.append(r)
         del wl
     head = results[0]
+    served = "served" in head
     line = {
-        "metric": "decoded GVoxel/s (bit-exact), batched",
+        "metric": "decoded GVoxel/s (bit-exact) batched vs plain; p50/p99 brick-request latency",
         "value": head["value"] if head["bit_exact"] else None,
         "unit": "GVoxel/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        # served workload: a step is one request of the measured trace
+        "steps": args.serve_requests if served else args.steps,
+        "warmup": args.serve_warmup if served else args.warmup,
         "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
@@ -441,6 +613,8 @@ def main():
         line["cpu_baseline"] = head["cpu_baseline"]
     if "plain" in head:
         line["plain"] = head["plain"]
+    if served:
+        line["served"] = head["served"]
     line["secondary"] = results[1:]
     line["env"] = dict(host_info(), gpu=torch.cuda.get_device_name(dev), kernel_source=kernel_source_hash())
     print(json.dumps(line), flush=True)

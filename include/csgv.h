@@ -273,6 +273,9 @@ typedef struct {
     /* pairs_requested = hits (resident) + joined (already queued or in flight) + decoded */
     uint64_t requests_done, pairs_requested, hits, joined, decoded, evictions, resets, batches;
     uint64_t decoded_elements, requested_elements, cache_top, resident, pinned, failed_tasks;
+    uint64_t splits;          /* slots of a larger class split to provide slots of a smaller one */
+    uint64_t record_bytes;    /* compressed record bytes of every decoded pair (algorithmic reads) */
+    double kernel_ms;         /* decode-kernel time of every batch, HIP events on the batch's stream */
     uint32_t max_batch_seen;
 } csgv_server_stats;
 

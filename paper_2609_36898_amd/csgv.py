@@ -302,10 +302,11 @@ class ServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("requests_done", "pairs_requested", "hits", "joined", "decoded",
                                                "evictions", "resets", "batches", "decoded_elements",
                                                "requested_elements", "cache_top", "resident", "pinned",
-                                               "failed_tasks")] + [("max_batch_seen", ctypes.c_uint32)]
+                                               "failed_tasks", "splits", "record_bytes")] + \
+        [("kernel_ms", ctypes.c_double), ("max_batch_seen", ctypes.c_uint32)]
 
     def as_dict(self):
-        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+        return {f: (float if f == "kernel_ms" else int)(getattr(self, f)) for f, _ in self._fields_}
 
 
 _lib.csgv_server_create.argtypes = [ctypes.POINTER(VolumeInfo), _P, _P, _P, _U64, ctypes.POINTER(ServerConfig),

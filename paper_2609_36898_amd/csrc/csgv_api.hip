@@ -181,7 +181,8 @@ hipError_t enqueue_persistent(Params P, const Bufs& b, const csgv_volume_info* v
         P.dense_offs = b.dense;
         if ((e = launch_dense_offsets(P, b.dense, s)) != hipSuccess) return e;
     }
-    if (sort) {
+    // with no more tasks than work-groups every task starts at once: order is moot
+    if (sort && P.n_tasks > grid) {
         if ((e = launch_sort(P, b.cls, b.hist, b.order, s)) != hipSuccess) return e;
         P.order = b.order;
     }

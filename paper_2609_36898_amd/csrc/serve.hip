@@ -21,13 +21,10 @@ struct GpuBackend {
         hipStream_t stream = nullptr;
         csgv_plan* plan = nullptr;
         hipEvent_t done = nullptr;
-        uint32_t* h_ids = nullptr;
-        uint8_t* h_lods = nullptr;
-        uint64_t* h_offs = nullptr;
+        // one pinned staging block per batch: offsets | ids | LODs (one copy to the device)
+        uint8_t* h_tasks = nullptr;
+        uint8_t* d_tasks = nullptr;
         uint32_t* h_status = nullptr;
-        uint32_t* d_ids = nullptr;
-        uint8_t* d_lods = nullptr;
-        uint64_t* d_offs = nullptr;
         uint32_t* d_status = nullptr;
         uint32_t n = 0;
         bool busy = false;
@@ -39,6 +36,9 @@ struct GpuBackend {
     hipError_t err = hipSuccess;
     csgv_status plan_err = CSGV_OK;
     uint64_t failed_tasks = 0;
+    std::vector<uint64_t> rec_off;  // host copy of the container's record offsets
+    uint64_t record_bytes = 0;
+    double kernel_ms = 0;
 
     int streams() const { return (int)lanes.size(); }
     bool busy(int s) { return lanes[s].busy; }
@@ -49,21 +49,23 @@ struct GpuBackend {
         if (e == hipErrorNotReady) return false;
         if (e != hipSuccess && err == hipSuccess) err = e;
         for (uint32_t j = 0; j < l.n; ++j) failed_tasks += l.h_status[j] != 0;
+        float ms = 0;
+        if (csgv_plan_last_kernel_ms(l.plan, &ms) == CSGV_OK) kernel_ms += ms;
         l.busy = false;
         return true;
     }
     void launch(int s, const uint32_t* ids, const uint8_t* lods, const uint64_t* offs, uint32_t n) {
         Lane& l = lanes[s];
-        memcpy(l.h_ids, ids, 4ull * n);
-        memcpy(l.h_lods, lods, n);
-        memcpy(l.h_offs, offs, 8ull * n);
+        memcpy(l.h_tasks, offs, 8ull * n);
+        memcpy(l.h_tasks + 8ull * n, ids, 4ull * n);
+        memcpy(l.h_tasks + 12ull * n, lods, n);
+        for (uint32_t j = 0; j < n; ++j) record_bytes += rec_off[ids[j] + 1] - rec_off[ids[j]];
         l.n = n;
         l.busy = true;
-        hipError_t e = hipMemcpyAsync(l.d_ids, l.h_ids, 4ull * n, hipMemcpyHostToDevice, l.stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(l.d_lods, l.h_lods, n, hipMemcpyHostToDevice, l.stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(l.d_offs, l.h_offs, 8ull * n, hipMemcpyHostToDevice, l.stream);
+        hipError_t e = hipMemcpyAsync(l.d_tasks, l.h_tasks, 13ull * n, hipMemcpyHostToDevice, l.stream);
         if (e == hipSuccess) {
-            const csgv_status st = csgv_plan_launch(l.plan, l.stream, container, l.d_ids, l.d_lods, l.d_offs, n, cache,
+            const csgv_status st = csgv_plan_launch(l.plan, l.stream, container, (const uint32_t*)(l.d_tasks + 8ull * n),
+                                                    l.d_tasks + 12ull * n, (const uint64_t*)l.d_tasks, n, cache,
                                                     cache_elems, l.d_status);
             if (st != CSGV_OK && plan_err == CSGV_OK) plan_err = st;
         }
@@ -103,13 +105,9 @@ void destroy_lanes(GpuBackend& be) {
         if (l.plan) csgv_plan_destroy(l.plan);
         if (l.done) (void)hipEventDestroy(l.done);
         if (l.stream) (void)hipStreamDestroy(l.stream);
-        if (l.h_ids) (void)hipHostFree(l.h_ids);
-        if (l.h_lods) (void)hipHostFree(l.h_lods);
-        if (l.h_offs) (void)hipHostFree(l.h_offs);
+        if (l.h_tasks) (void)hipHostFree(l.h_tasks);
         if (l.h_status) (void)hipHostFree(l.h_status);
-        if (l.d_ids) (void)hipFree(l.d_ids);
-        if (l.d_lods) (void)hipFree(l.d_lods);
-        if (l.d_offs) (void)hipFree(l.d_offs);
+        if (l.d_tasks) (void)hipFree(l.d_tasks);
         if (l.d_status) (void)hipFree(l.d_status);
     }
     be.lanes.clear();
@@ -143,12 +141,10 @@ csgv_status csgv_server_create(const csgv_volume_info* vol, const void* d_contai
     for (auto& l : s->be.lanes) {
         if (hipStreamCreateWithFlags(&l.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&l.done, hipEventDisableTiming) != hipSuccess ||
-            hipHostMalloc((void**)&l.h_ids, 4ull * max_batch, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void**)&l.h_lods, max_batch, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void**)&l.h_offs, 8ull * max_batch, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&l.h_tasks, 13ull * max_batch, hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc((void**)&l.h_status, 4ull * max_batch, hipHostMallocDefault) != hipSuccess ||
-            hipMalloc(&l.d_ids, 4ull * max_batch) != hipSuccess || hipMalloc(&l.d_lods, max_batch) != hipSuccess ||
-            hipMalloc(&l.d_offs, 8ull * max_batch) != hipSuccess || hipMalloc(&l.d_status, 4ull * max_batch) != hipSuccess) {
+            hipMalloc((void**)&l.d_tasks, 13ull * max_batch) != hipSuccess ||
+            hipMalloc((void**)&l.d_status, 4ull * max_batch) != hipSuccess) {
             destroy_lanes(s->be);
             delete s;
             return serve_fail(CSGV_ENOMEM, "server stream resources");
@@ -160,6 +156,15 @@ csgv_status csgv_server_create(const csgv_volume_info* vol, const void* d_contai
             return serve_fail(st, csgv_last_error());
         }
         (void)csgv_plan_set_graph(l.plan, 0);  // batches differ in size: direct launches
+        (void)csgv_plan_set_timing(l.plan, 1);
+    }
+    // record offsets (the parsed volume guarantees they lie inside the container)
+    s->be.rec_off.resize((size_t)vol->n_bricks + 1);
+    if (hipMemcpy(s->be.rec_off.data(), (const uint8_t*)d_container + vol->offsets_pos, 8ull * (vol->n_bricks + 1),
+                  hipMemcpyDeviceToHost) != hipSuccess) {
+        destroy_lanes(s->be);
+        delete s;
+        return serve_fail(CSGV_EHIP, "reading the record offsets");
     }
     s->sched = new csgv::Scheduler<GpuBackend>(s->be, cache_elements, l2.data(), vol->n_bricks, max_batch,
                                                cfg && cfg->keep_pinned);
@@ -215,23 +220,29 @@ csgv_status csgv_server_where(csgv_server* s, uint32_t id, uint8_t lod, uint64_t
 csgv_status csgv_server_run(csgv_server* s, const uint32_t* h_ids, const uint8_t* h_lods, const uint64_t* h_req_start,
                             uint32_t n_req, const double* h_arrival, csgv_request_done* out) {
     if (!s || !h_req_start || (n_req && (!h_arrival || !out))) return serve_fail(CSGV_EINVAL, "NULL argument");
+    for (uint32_t r = 0; r < n_req; ++r) {
+        if (h_req_start[r + 1] < h_req_start[r]) return serve_fail(CSGV_EINVAL, "request starts not ordered");
+        if (r && h_arrival[r] < h_arrival[r - 1]) return serve_fail(CSGV_EINVAL, "arrivals not ordered");
+    }
     const double base = csgv_server_clock(s);
     std::vector<uint64_t> ids(n_req);
-    for (uint32_t r = 0; r < n_req; ++r) {
-        const uint64_t a = h_req_start[r], b = h_req_start[r + 1];
-        if (b < a) return serve_fail(CSGV_EINVAL, "request starts not ordered");
-        if (!s->sched->submit(h_ids + a, h_lods + a, (uint32_t)(b - a), base + h_arrival[r], &ids[r]))
-            return serve_fail(CSGV_EINVAL, "a pair names no brick, or a LOD beyond the brick side");
-    }
-    const uint64_t first = n_req ? ids[0] : 0;
-    uint32_t done = 0;
+    uint32_t next = 0, done = 0;
+    uint64_t first = 0;
     while (done < n_req) {
+        // requests are handed to the scheduler as they arrive
+        const double now = csgv_server_clock(s);
+        for (; next < n_req && base + h_arrival[next] <= now; ++next) {
+            const uint64_t a = h_req_start[next], b = h_req_start[next + 1];
+            if (!s->sched->submit(h_ids + a, h_lods + a, (uint32_t)(b - a), base + h_arrival[next], &ids[next]))
+                return serve_fail(CSGV_EINVAL, "a pair names no brick, or a LOD beyond the brick side");
+            if (next == 0) first = ids[0];
+        }
         s->sched->step(csgv_server_clock(s));
         const csgv_status st = backend_status(s);
         if (st != CSGV_OK) return st;
         for (const csgv::ServeDone& d : s->sched->drain()) {
             const uint64_t r = d.req - first;
-            if (d.req >= first && r < n_req) {
+            if (next > 0 && d.req >= first && r < n_req) {
                 memcpy(&out[r], &d, sizeof(d));
                 out[r].t_arrival -= base;
                 out[r].t_admit -= base;
@@ -241,11 +252,10 @@ csgv_status csgv_server_run(csgv_server* s, const uint32_t* h_ids, const uint8_t
                 s->done.push_back(d);  // a request submitted outside this run
             }
         }
-        // idle until the next arrival when nothing is in flight
-        if (s->sched->in_flight() == 0) {
-            const double na = s->sched->next_arrival();
-            const double now = csgv_server_clock(s);
-            if (na > now + 2e-4) std::this_thread::sleep_for(std::chrono::duration<double>(na - now - 1e-4));
+        // idle until the next arrival when nothing is waiting, queued or in flight
+        if (s->sched->in_flight() == 0 && next < n_req && s->sched->next_arrival() < 0) {
+            const double na = base + h_arrival[next], t = csgv_server_clock(s);
+            if (na > t + 2e-4) std::this_thread::sleep_for(std::chrono::duration<double>(na - t - 1e-4));
         }
     }
     return CSGV_OK;
@@ -268,6 +278,9 @@ csgv_status csgv_server_get_stats(csgv_server* s, csgv_server_stats* out) {
     out->resident = t.resident;
     out->pinned = t.pinned;
     out->failed_tasks = s->be.failed_tasks;
+    out->splits = t.splits;
+    out->record_bytes = s->be.record_bytes;
+    out->kernel_ms = s->be.kernel_ms;
     out->max_batch_seen = t.max_batch_seen;
     return CSGV_OK;
 }

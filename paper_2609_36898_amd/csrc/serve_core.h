@@ -11,10 +11,11 @@
 // (id, LOD); entries are pinned while a request that needs them is pending,
 // and unpinned resident entries form a per-class LRU list that provisioning
 // evicts from.  Requests are admitted strictly in arrival order when every
-// pair is resident, in flight, or can be given a slot (free list of its
-// class, cache top, or the least recently used unpinned entry of its class);
-// a request that cannot be admitted waits, and a full cache with nothing
-// pinned is reset.  Admitted misses queue as decode tasks; whenever a
+// pair is resident, in flight, or can be given a slot: the free list of its
+// class, the cache top, the least recently used unpinned entry of its class,
+// or a slot of a larger class (free, else its least recently used entry)
+// split into slots of this class.  A request that cannot be admitted waits,
+// and a full cache with nothing pinned is reset.  Admitted misses queue as decode tasks; whenever a
 // backend stream is free, up to max_batch queued tasks are launched on it
 // (continuous batching: requests admitted while earlier batches run get
 // their own batches on the other streams).  A request completes when the
@@ -31,7 +32,6 @@
 
 #include <algorithm>
 #include <deque>
-#include <list>
 #include <unordered_map>
 #include <vector>
 
@@ -47,7 +47,7 @@ struct ServeDone {
 struct ServeStats {
     // pairs_requested = hits (resident) + joined (queued or in flight for another request) + decoded
     uint64_t requests_done = 0, pairs_requested = 0, hits = 0, joined = 0, decoded = 0, evictions = 0, resets = 0,
-             batches = 0;
+             batches = 0, splits = 0;
     uint64_t decoded_elements = 0, requested_elements = 0, top = 0, resident = 0, pinned = 0;
     uint32_t max_batch_seen = 0;
 };
@@ -62,9 +62,12 @@ public:
               bool keep_pinned)
         : be_(be), cap_(cache_elems), max_batch_(max_batch ? max_batch : 1), keep_pinned_(keep_pinned) {
         l2_.assign(brick_log2b, brick_log2b + n_bricks);
+        slot_.assign((size_t)n_bricks * 8, 0u);
+        stamp_.assign((size_t)n_bricks * 8, 0u);
         for (uint32_t c = 0; c < kClasses; ++c) cls_elems_.push_back(uint64_t(1) << (3 * c));
         free_.resize(kClasses);
-        lru_.resize(kClasses);
+        head_.assign(kClasses, kNil);
+        tail_.assign(kClasses, kNil);
         batches_.resize(be_.streams());
     }
 
@@ -73,16 +76,25 @@ public:
     bool submit(const uint32_t* ids, const uint8_t* lods, uint32_t n, double t_arrival, uint64_t* req) {
         for (uint32_t j = 0; j < n; ++j)
             if (ids[j] >= l2_.size() || lods[j] > l2_[ids[j]]) return false;
+        if (++stamp_now_ == 0) {  // wrapped: forget every stamp
+            std::fill(stamp_.begin(), stamp_.end(), 0u);
+            stamp_now_ = 1;
+        }
         Req r;
         r.id = next_req_++;
         r.t_arr = t_arrival;
         r.keys.reserve(n);
-        for (uint32_t j = 0; j < n; ++j) r.keys.push_back(key_of(ids[j], lods[j]));
-        std::sort(r.keys.begin(), r.keys.end());
-        r.keys.erase(std::unique(r.keys.begin(), r.keys.end()), r.keys.end());
+        for (uint32_t j = 0; j < n; ++j) {
+            const uint64_t k = key_of(ids[j], lods[j]);
+            if (stamp_[k] != stamp_now_) {
+                stamp_[k] = stamp_now_;
+                r.keys.push_back(k);
+            }
+        }
         *req = r.id;
-        waiting_.push_back(r.id);
-        reqs_.emplace(r.id, std::move(r));
+        if (reqs_.empty()) req_base_ = r.id;
+        reqs_.push_back(std::move(r));
+        waiting_.push_back(*req);
         return true;
     }
 
@@ -96,16 +108,12 @@ public:
         for (int s = 0; s < (int)batches_.size(); ++s)
             if (!batches_[s].empty() && be_.poll(s)) retire(s, now);
         while (!waiting_.empty()) {
-            Req& r = reqs_.at(waiting_.front());
+            Req& r = req(waiting_.front());
             if (r.t_arr > now) break;
             if (!admit(r, now)) {
                 if (can_reset()) {
                     reset();
-                    if (admit(r, now)) {
-                        waiting_.pop_front();
-                        continue;
-                    }
-                    reject(r, now);  // larger than the whole cache
+                    if (!admit(r, now)) reject(r, now);  // larger than the whole cache
                     waiting_.pop_front();
                     continue;
                 }
@@ -115,6 +123,7 @@ public:
         }
         for (int s = 0; s < (int)batches_.size() && !queued_.empty(); ++s)
             if (batches_[s].empty() && !be_.busy(s)) launch(s);
+        drop_finished();
         return !waiting_.empty() || !queued_.empty() || in_flight() > 0;
     }
 
@@ -136,15 +145,14 @@ public:
 
     // element offset of a resident pair (false if not resident)
     bool where(uint32_t id, uint8_t lod, uint64_t* off) const {
-        auto it = map_.find(key_of(id, lod));
-        if (it == map_.end() || it->second.state != kResident) return false;
-        *off = it->second.off;
+        if (id >= l2_.size() || lod > 7) return false;
+        const uint32_t e = slot_[key_of(id, lod)];
+        if (!e || ent_[e - 1].state != kResident) return false;
+        *off = ent_[e - 1].off;
         return true;
     }
 
-    double next_arrival() const {
-        return waiting_.empty() ? -1.0 : reqs_.at(waiting_.front()).t_arr;
-    }
+    double next_arrival() const { return waiting_.empty() ? -1.0 : reqs_[waiting_.front() - req_base_].t_arr; }
     uint32_t in_flight() const {
         uint32_t n = 0;
         for (auto& b : batches_) n += b.empty() ? 0 : 1;
@@ -152,31 +160,85 @@ public:
     }
     const ServeStats& stats() {
         st_.top = top_;
-        st_.resident = map_.size();
-        uint64_t p = 0;
-        for (auto& kv : map_) p += kv.second.pins ? 1 : 0;
-        st_.pinned = p;
+        st_.resident = n_live_;
+        st_.pinned = n_pinned_;
         return st_;
     }
 
 private:
     enum { kQueued = 0, kFlight = 1, kResident = 2 };
+    static constexpr uint32_t kNil = 0xFFFFFFFFu;
+    // a cache entry (pair resident, queued or in flight); slot_[key] = index + 1
     struct Entry {
-        uint64_t off = 0;
-        uint32_t cls = 0, pins = 0;
-        int state = kQueued;
+        uint64_t off = 0, key = 0;
+        uint32_t pins = 0, prev = kNil, next = kNil;  // LRU links while unpinned and resident
+        uint8_t cls = 0, state = kQueued;
+        bool in_lru = false, live = false;
         std::vector<uint64_t> waiters;  // requests waiting for this pair
-        std::list<uint64_t>::iterator lru;
-        bool in_lru = false;
     };
     struct Req {
         uint64_t id = 0;
         double t_arr = 0, t_adm = 0;
         std::vector<uint64_t> keys;
         uint32_t pending = 0, n_decoded = 0;
+        bool finished = false;
     };
-    static uint64_t key_of(uint32_t id, uint8_t lod) { return ((uint64_t)id << 8) | lod; }
-    uint32_t class_of(uint64_t k) const { return l2_[(uint32_t)(k >> 8)] - (uint32_t)(k & 0xFF); }
+    static uint64_t key_of(uint32_t id, uint8_t lod) { return (uint64_t)id * 8 + lod; }
+    uint32_t class_of(uint64_t k) const { return l2_[k >> 3] - (uint32_t)(k & 7); }
+    Req& req(uint64_t id) { return reqs_[id - req_base_]; }
+    Entry* find(uint64_t k) { return slot_[k] ? &ent_[slot_[k] - 1] : nullptr; }
+
+    uint32_t create(uint64_t k, uint64_t off, uint32_t cls) {
+        uint32_t i;
+        if (!ent_free_.empty()) {
+            i = ent_free_.back();
+            ent_free_.pop_back();
+        } else {
+            i = (uint32_t)ent_.size();
+            ent_.emplace_back();
+        }
+        Entry& e = ent_[i];
+        e.off = off;
+        e.key = k;
+        e.cls = (uint8_t)cls;
+        e.pins = 1;
+        e.state = kQueued;
+        e.in_lru = false;
+        e.live = true;
+        e.waiters.clear();
+        slot_[k] = i + 1;
+        ++n_live_;
+        ++n_pinned_;
+        return i;
+    }
+    void erase(uint32_t i) {
+        Entry& e = ent_[i];
+        slot_[e.key] = 0;
+        e.live = false;
+        e.waiters.clear();
+        ent_free_.push_back(i);
+        --n_live_;
+    }
+
+    // per-class LRU list, most recent at the head
+    void lru_push(uint32_t i) {
+        Entry& e = ent_[i];
+        e.prev = kNil;
+        e.next = head_[e.cls];
+        if (e.next != kNil) ent_[e.next].prev = i;
+        else tail_[e.cls] = i;
+        head_[e.cls] = i;
+        e.in_lru = true;
+    }
+    void lru_remove(uint32_t i) {
+        Entry& e = ent_[i];
+        if (e.prev != kNil) ent_[e.prev].next = e.next;
+        else head_[e.cls] = e.next;
+        if (e.next != kNil) ent_[e.next].prev = e.prev;
+        else tail_[e.cls] = e.prev;
+        e.prev = e.next = kNil;
+        e.in_lru = false;
+    }
 
     bool alloc(uint32_t cls, uint64_t* off) {
         if (!free_[cls].empty()) {
@@ -189,109 +251,122 @@ private:
             top_ += cls_elems_[cls];
             return true;
         }
-        if (!lru_[cls].empty()) {  // least recently used unpinned resident pair of this class
-            const uint64_t victim = lru_[cls].back();
-            lru_[cls].pop_back();
-            auto it = map_.find(victim);
-            *off = it->second.off;
-            map_.erase(it);
-            ++st_.evictions;
+        if (tail_[cls] != kNil) {  // least recently used unpinned resident pair of this class
+            *off = evict_lru(cls);
             return true;
+        }
+        // split a slot of the nearest larger class: a free one first, else its LRU entry
+        for (int pass = 0; pass < 2; ++pass) {
+            for (uint32_t c = cls + 1; c < kClasses; ++c) {
+                uint64_t big;
+                if (pass == 0 && !free_[c].empty()) {
+                    big = free_[c].back();
+                    free_[c].pop_back();
+                } else if (pass == 1 && tail_[c] != kNil) {
+                    big = evict_lru(c);
+                } else {
+                    continue;
+                }
+                const uint64_t n = cls_elems_[c] / cls_elems_[cls];
+                for (uint64_t q = n - 1; q >= 1; --q) free_[cls].push_back(big + q * cls_elems_[cls]);
+                *off = big;
+                ++st_.splits;
+                return true;
+            }
         }
         return false;
     }
 
-    void pin(uint64_t k, Entry& e) {
-        (void)k;
-        if (e.in_lru) {
-            lru_[e.cls].erase(e.lru);
-            e.in_lru = false;
-        }
-        ++e.pins;
+    uint64_t evict_lru(uint32_t cls) {
+        const uint32_t v = tail_[cls];
+        lru_remove(v);
+        const uint64_t off = ent_[v].off;
+        erase(v);
+        ++st_.evictions;
+        return off;
+    }
+
+    void pin(Entry& e, uint32_t i) {
+        if (e.in_lru) lru_remove(i);
+        if (e.pins++ == 0) ++n_pinned_;
     }
     void unpin(uint64_t k) {
-        auto it = map_.find(k);
-        if (it == map_.end()) return;
-        Entry& e = it->second;
-        if (e.pins && --e.pins == 0 && e.state == kResident) {
-            lru_[e.cls].push_front(k);
-            e.lru = lru_[e.cls].begin();
-            e.in_lru = true;
+        const uint32_t s = slot_[k];
+        if (!s) return;
+        Entry& e = ent_[s - 1];
+        if (e.pins && --e.pins == 0) {
+            --n_pinned_;
+            if (e.state == kResident) lru_push(s - 1);
         }
     }
 
     bool admit(Req& r, double now) {
-        std::vector<uint64_t> pinned, created;
-        for (uint64_t k : r.keys) {
-            auto it = map_.find(k);
-            if (it != map_.end()) {
-                pin(k, it->second);
-                pinned.push_back(k);
+        created_.clear();
+        for (size_t j = 0; j < r.keys.size(); ++j) {
+            const uint64_t k = r.keys[j];
+            if (const uint32_t s = slot_[k]) {
+                pin(ent_[s - 1], s - 1);
                 continue;
             }
             const uint32_t cls = class_of(k);
             uint64_t off;
             if (!alloc(cls, &off)) {
-                rollback(pinned, created);
+                rollback(r, j);
                 return false;
             }
-            Entry e;
-            e.off = off;
-            e.cls = cls;
-            e.pins = 1;
-            e.state = kQueued;
-            map_.emplace(k, std::move(e));
-            created.push_back(k);
-            pinned.push_back(k);
+            create(k, off, cls);
+            created_.push_back(k);
         }
         r.t_adm = now;
         r.pending = 0;
         for (uint64_t k : r.keys) {
-            Entry& e = map_.at(k);
+            Entry& e = ent_[slot_[k] - 1];
             if (e.state != kResident) {
                 e.waiters.push_back(r.id);
                 ++r.pending;
             } else {
                 ++st_.hits;
             }
+            st_.requested_elements += cls_elems_[e.cls];
         }
-        st_.joined += r.pending - created.size();
-        for (uint64_t k : created) queued_.push_back(k);
-        r.n_decoded = (uint32_t)created.size();
+        st_.joined += r.pending - created_.size();
+        for (uint64_t k : created_) queued_.push_back(k);
+        r.n_decoded = (uint32_t)created_.size();
         st_.pairs_requested += r.keys.size();
-        for (uint64_t k : r.keys) st_.requested_elements += cls_elems_[class_of(k)];
         if (r.pending == 0) finish(r, now);
         return true;
     }
 
-    void rollback(const std::vector<uint64_t>& pinned, const std::vector<uint64_t>& created) {
-        for (uint64_t k : created) {
-            auto it = map_.find(k);
-            free_[it->second.cls].push_back(it->second.off);
-            map_.erase(it);
+    // undo the first n_done keys of a failed admission: entries created by it
+    // give their slots back (and are gone), the others are unpinned
+    void rollback(Req& r, size_t n_done) {
+        for (uint64_t k : created_) {
+            const uint32_t s = slot_[k];
+            free_[ent_[s - 1].cls].push_back(ent_[s - 1].off);
+            --n_pinned_;
+            erase(s - 1);
         }
-        for (uint64_t k : pinned) {
-            if (std::find(created.begin(), created.end(), k) != created.end()) continue;
-            unpin(k);
-        }
+        for (size_t j = 0; j < n_done; ++j)
+            if (slot_[r.keys[j]]) unpin(r.keys[j]);
+        created_.clear();
     }
 
     void reject(Req& r, double now) {
         ServeDone d{r.id, r.t_arr, now, now, (uint32_t)r.keys.size(), 0, -1};
         done_.push_back(d);
-        reqs_.erase(r.id);
+        r.finished = true;
+        r.keys = std::vector<uint64_t>();
     }
 
     bool can_reset() const {
-        if (!queued_.empty() || in_flight() > 0 || !held_.empty() || !to_unpin_.empty()) return false;
-        for (auto& kv : map_)
-            if (kv.second.pins) return false;
-        return true;
+        return queued_.empty() && in_flight() == 0 && held_.empty() && to_unpin_.empty() && n_pinned_ == 0;
     }
     void reset() {
-        map_.clear();
+        for (uint32_t i = 0; i < (uint32_t)ent_.size(); ++i)
+            if (ent_[i].live) erase(i);
         for (auto& f : free_) f.clear();
-        for (auto& l : lru_) l.clear();
+        std::fill(head_.begin(), head_.end(), kNil);
+        std::fill(tail_.begin(), tail_.end(), kNil);
         top_ = 0;
         ++st_.resets;
     }
@@ -304,11 +379,11 @@ private:
         while (!queued_.empty() && b.size() < max_batch_) {
             const uint64_t k = queued_.front();
             queued_.pop_front();
-            Entry& e = map_.at(k);
+            Entry& e = ent_[slot_[k] - 1];
             e.state = kFlight;
             b.push_back(k);
-            ids_.push_back((uint32_t)(k >> 8));
-            lods_.push_back((uint8_t)(k & 0xFF));
+            ids_.push_back((uint32_t)(k >> 3));
+            lods_.push_back((uint8_t)(k & 7));
             offs_.push_back(e.off);
             st_.decoded_elements += cls_elems_[e.cls];
         }
@@ -320,14 +395,16 @@ private:
 
     void retire(int s, double now) {
         for (uint64_t k : batches_[s]) {
-            Entry& e = map_.at(k);
+            Entry& e = ent_[slot_[k] - 1];
             e.state = kResident;
-            std::vector<uint64_t> w;
-            w.swap(e.waiters);
-            for (uint64_t rid : w) {
-                Req& r = reqs_.at(rid);
+            waiters_tmp_.swap(e.waiters);
+            for (uint64_t rid : waiters_tmp_) {
+                Req& r = req(rid);
                 if (--r.pending == 0) finish(r, now);
             }
+            waiters_tmp_.clear();
+            // a pair whose requests all completed earlier (rollback) is unpinned and resident now
+            if (e.pins == 0 && !e.in_lru) lru_push(slot_[k] - 1);
         }
         batches_[s].clear();
     }
@@ -336,9 +413,17 @@ private:
         ServeDone d{r.id, r.t_arr, r.t_adm, now, (uint32_t)r.keys.size(), r.n_decoded, 0};
         done_.push_back(d);
         ++st_.requests_done;
-        if (keep_pinned_) held_.emplace(r.id, r.keys);
+        if (keep_pinned_) held_.emplace(r.id, std::move(r.keys));
         else to_unpin_.insert(to_unpin_.end(), r.keys.begin(), r.keys.end());
-        reqs_.erase(r.id);
+        r.keys = std::vector<uint64_t>();
+        r.finished = true;
+    }
+
+    void drop_finished() {
+        while (!reqs_.empty() && reqs_.front().finished) {
+            reqs_.pop_front();
+            ++req_base_;
+        }
     }
 
     Backend& be_;
@@ -346,11 +431,17 @@ private:
     uint32_t max_batch_;
     bool keep_pinned_;
     std::vector<uint8_t> l2_;
+    std::vector<uint32_t> slot_;   // (id * 8 + LOD) -> entry index + 1, 0 when absent
+    std::vector<uint32_t> stamp_;  // duplicate pairs within one submitted request
+    uint32_t stamp_now_ = 0;
+    std::vector<Entry> ent_;
+    std::vector<uint32_t> ent_free_;
+    uint64_t n_live_ = 0, n_pinned_ = 0;  // live entries; entries with pins > 0
     std::vector<uint64_t> cls_elems_;
     std::vector<std::vector<uint64_t>> free_;
-    std::vector<std::list<uint64_t>> lru_;
-    std::unordered_map<uint64_t, Entry> map_;
-    std::unordered_map<uint64_t, Req> reqs_;
+    std::vector<uint32_t> head_, tail_;  // per-class LRU list ends
+    std::deque<Req> reqs_;               // requests by id, from req_base_ on
+    uint64_t req_base_ = 0;
     std::unordered_map<uint64_t, std::vector<uint64_t>> held_;
     std::deque<uint64_t> waiting_;  // request ids in arrival order
     std::deque<uint64_t> queued_;   // pairs waiting for a batch
@@ -360,6 +451,7 @@ private:
     std::vector<uint32_t> ids_;
     std::vector<uint8_t> lods_;
     std::vector<uint64_t> offs_;
+    std::vector<uint64_t> created_, waiters_tmp_;
     uint64_t next_req_ = 0;
     ServeStats st_;
 };

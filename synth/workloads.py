@@ -72,37 +72,66 @@ def frustum_requests(n_requests: int, grid, rate_hz: float, brick: int = 32, see
     voxel per pixel.  The request is n ~ log-uniform[1, n_max] bricks drawn
     without replacement from the visible ones.
 
+    Grids of more than 2^16 bricks test visibility on random candidates
+    (doubling their number until n visible ones are found, or every brick has
+    been tested), which draws from the same distribution without evaluating
+    every brick for every request.  The arrival times scale with 1 / rate_hz
+    and the requests themselves do not depend on it.
+
     Returns (ids u32, lods u8, starts u64[n+1], arrivals f64[n] in seconds).
     """
     rng = np.random.default_rng(seed + 7001)
     nbx, nby, nbz = grid
+    nb = nbx * nby * nbz
     extent = float(brick * max(grid))
-    g = np.stack(np.meshgrid(np.arange(nbx), np.arange(nby), np.arange(nbz), indexing="ij"), -1).reshape(-1, 3)
-    bid = (g[:, 0] + nbx * (g[:, 1] + nby * g[:, 2])).astype(np.uint32)
-    centres = ((g.astype(np.float64) + 0.5) * brick).astype(np.float32)
-    cc = (centres.astype(np.float64) ** 2).sum(1)
     vol_c = np.array([nbx, nby, nbz], np.float64) * brick * 0.5
     half = np.deg2rad(fov_deg) / 2
     cos_half = np.cos(half)
     arrivals = np.cumsum(rng.exponential(1.0 / rate_hz, size=n_requests))
+
+    def geometry(b, v, cam):
+        """distance and visibility of bricks b (flat ids, x fastest) from camera cam looking along -v"""
+        b = np.asarray(b, dtype=np.int64)
+        c = np.stack([b % nbx, (b // nbx) % nby, b // (nbx * nby)], 1).astype(np.float32)
+        c = (c + np.float32(0.5)) * np.float32(brick)
+        cc = (c.astype(np.float64) ** 2).sum(1)
+        # centre . (-v) and centre . cam in one product
+        dots = c @ np.stack([-v, cam], 1).astype(np.float32)
+        dist = np.sqrt(np.maximum(cc - 2.0 * dots[:, 1] + cam @ cam, 0.0))
+        along = dots[:, 0] + cam @ v  # (centre - cam) . (-v)
+        return dist, along >= cos_half * dist
+
+    every = np.arange(nb, dtype=np.int64) if nb <= (1 << 16) else None
     ids, lods, starts = [], [], [0]
     for _ in range(n_requests):
         v = rng.normal(size=3)
         v /= np.linalg.norm(v)
         cam = vol_c + v * (extent * rng.uniform(*orbit))
-        # centre . (-v) and centre . cam for every brick in one product
-        dots = centres @ np.stack([-v, cam], 1).astype(np.float32)
-        dist = np.sqrt(np.maximum(cc - 2.0 * dots[:, 1] + cam @ cam, 0.0))
-        along = dots[:, 0] + cam @ v  # (centre - cam) . (-v)
-        vis = np.nonzero(along >= cos_half * dist)[0]
         n = int(round(np.exp(rng.uniform(0.0, np.log(n_max)))))
-        if len(vis) == 0:
-            vis = np.array([int(np.argmin(dist))])
-        n = max(1, min(n, len(vis)))
-        pick = rng.choice(vis, size=n, replace=False)
-        lod = np.floor(np.log2(np.maximum(2 * dist[pick] * np.tan(half) / screen_h, 1e-9)))
-        ids.append(bid[pick])
+        pick = None
+        if every is None:
+            m = max(4 * n, 4096)
+            while m < nb:
+                cand = np.unique(rng.integers(0, nb, size=m))
+                rng.shuffle(cand)
+                dist, vis = geometry(cand, v, cam)
+                if vis.sum() >= n:
+                    sel = np.nonzero(vis)[0][:n]
+                    pick, pdist = cand[sel], dist[sel]
+                    break
+                m *= 2
+        if pick is None:
+            allb = every if every is not None else np.arange(nb, dtype=np.int64)
+            dist, vis = geometry(allb, v, cam)
+            vis = np.nonzero(vis)[0]
+            if len(vis) == 0:
+                vis = np.array([int(np.argmin(dist))])
+            n = max(1, min(n, len(vis)))
+            sel = rng.choice(vis, size=n, replace=False)
+            pick, pdist = allb[sel], dist[sel]
+        lod = np.floor(np.log2(np.maximum(2 * pdist * np.tan(half) / screen_h, 1e-9)))
+        ids.append(pick.astype(np.uint32))
         lods.append(np.clip(lod, 0, max_lod).astype(np.uint8))
-        starts.append(starts[-1] + n)
+        starts.append(starts[-1] + len(pick))
     return (np.concatenate(ids).astype(np.uint32), np.concatenate(lods).astype(np.uint8),
             np.array(starts, dtype=np.uint64), arrivals)

@@ -116,9 +116,9 @@ extern "C" int sim_run(const uint8_t* l2p, uint32_t n_bricks, uint64_t cache_ele
     for (uint32_t r = 1; r < n_req && err.empty(); ++r)
         if (t_admit[r] < t_admit[r - 1]) err = "admission out of arrival order at request " + std::to_string(r);
     const csgv::ServeStats& s = sch.stats();
-    const uint64_t v[13] = {s.requests_done, s.pairs_requested, s.hits, s.decoded, s.evictions, s.resets,
+    const uint64_t v[14] = {s.requests_done, s.pairs_requested, s.hits, s.decoded, s.evictions, s.resets,
                             s.batches, s.decoded_elements, s.requested_elements, s.top, s.pinned, s.max_batch_seen,
-                            s.joined};
+                            s.joined, s.splits};
     memcpy(stats, v, sizeof(v));
     if (!err.empty()) {
         snprintf(errbuf, errcap, "%s", err.c_str());

@@ -35,7 +35,7 @@ def sim():
 
 
 STATS = ["requests_done", "pairs_requested", "hits", "decoded", "evictions", "resets", "batches",
-         "decoded_elements", "requested_elements", "top", "pinned", "max_batch_seen", "joined"]
+         "decoded_elements", "requested_elements", "top", "pinned", "max_batch_seen", "joined", "splits"]
 
 
 def run(lib, l2, cache, ids, lods, starts, arrival, streams=2, max_batch=64, keep_pinned=0, delay=3, dt=1e-3):
@@ -49,7 +49,7 @@ def run(lib, l2, cache, ids, lods, starts, arrival, streams=2, max_batch=64, kee
     t_done = np.zeros(n_req)
     status = np.zeros(n_req, dtype=np.int32)
     ndec = np.zeros(n_req, dtype=np.uint32)
-    stats = np.zeros(13, dtype=np.uint64)
+    stats = np.zeros(14, dtype=np.uint64)
     err = ctypes.create_string_buffer(512)
     rc = lib.sim_run(l2.ctypes.data, len(l2), cache, streams, max_batch, keep_pinned, delay, ids.ctypes.data,
                      lods.ctypes.data, starts.ctypes.data, n_req, arrival.ctypes.data, dt, t_adm.ctypes.data,
@@ -130,3 +130,45 @@ def test_hits_do_not_decode_again(sim):
     _, _, st, ndec, s = run(sim, l2, 1 << 20, ids, lods, starts, arr)
     assert (st == 0).all()
     assert list(ndec) == [2, 0, 0] and s["decoded"] == 2 and s["hits"] == 4
+
+
+def test_smaller_class_splits_a_larger_slot_instead_of_resetting(sim):
+    # two full bricks fill the cache; later requests for smaller LODs take
+    # slots split out of the least recently used full brick
+    l2 = np.full(8, 5, np.uint8)
+    ids = np.array([0, 1, 2, 3, 4, 1], np.uint32)
+    lods = np.array([0, 0, 1, 2, 1, 0], np.uint8)
+    starts = np.array([0, 2, 3, 4, 5, 6], np.uint64)
+    arr = np.array([0.0, 1.0, 2.0, 3.0, 4.0])
+    _, _, st, ndec, s = run(sim, l2, 2 * 32 ** 3, ids, lods, starts, arr, delay=2)
+    assert (st == 0).all()
+    assert s["resets"] == 0 and s["splits"] >= 1
+    # brick 0 (least recently used) was split; brick 1 stayed resident
+    assert list(ndec) == [2, 1, 1, 1, 0]
+
+
+def test_random_traces_keep_every_invariant(sim):
+    # small caches, brick sides 8..64, duplicate pairs, one to three streams,
+    # tiny batches, keep_pinned on and off: the simulation's own checks
+    # (no completed pair overwritten, slots inside the cache, arrival-order
+    # admission) must hold and every request must end served or rejected
+    rng = np.random.default_rng(0)
+    for trial in range(24):
+        nb = int(rng.integers(8, 200))
+        l2 = rng.choice(np.array([3, 4, 5, 6], np.uint8), size=nb)
+        reqs = []
+        for _ in range(int(rng.integers(20, 150))):
+            b = rng.integers(0, nb, size=int(rng.integers(1, 30))).astype(np.uint32)
+            reqs.append((b, np.array([rng.integers(0, l2[x] + 1) for x in b], np.uint8)))
+        ids = np.concatenate([a for a, _ in reqs])
+        lods = np.concatenate([b for _, b in reqs])
+        starts = np.concatenate([[0], np.cumsum([len(a) for a, _ in reqs])]).astype(np.uint64)
+        arr = np.sort(rng.uniform(0, 0.05, size=len(reqs)))
+        cache = int(rng.integers(1, 6)) * 64 ** 3
+        _, _, st, ndec, s = run(sim, l2, cache, ids, lods, starts, arr, streams=int(rng.integers(1, 4)),
+                                max_batch=int(rng.integers(1, 64)), keep_pinned=trial % 2,
+                                delay=int(rng.integers(1, 5)))
+        assert set(np.unique(st)) <= {0, -1}
+        assert s["requests_done"] == int((st == 0).sum())
+        assert s["hits"] + s["joined"] + s["decoded"] == s["pairs_requested"]
+        assert s["pinned"] == 0 and s["top"] <= cache
