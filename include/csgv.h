@@ -155,6 +155,28 @@ csgv_status csgv_decode_bricks(hipStream_t stream, const csgv_volume_info* vol, 
                                const csgv_decode_opts* opts);
 
 /*
+ * csgv_decode_bricks without allocating anything, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, outputs and errors, and
+ * nothing is allocated or freed: the scratch is a fixed device array of
+ * CSGV_NOALLOC_SCRATCH_BYTES inside the library, one per GPU it runs on, held
+ * until the process ends (its device address is looked up on the first call
+ * on each device).  Limits: at most CSGV_NOALLOC_MAX_TASKS tasks per call
+ * (else CSGV_EINVAL), and the persistent grid holds only as many work-groups
+ * as the array's scratch share fits (about 250 for 32^3 bricks, 75 for 64^3),
+ * so large batches run slower than with csgv_decode_bricks.  Every call on a
+ * GPU uses that GPU's one array: calls that overlap on one GPU (other streams,
+ * other threads) race and must be serialised by the caller.  The array keeps
+ * the last call's contents; each call resets what it needs with kernels.
+ */
+#define CSGV_NOALLOC_SCRATCH_BYTES (128ull << 20)
+#define CSGV_NOALLOC_MAX_TASKS 262144u
+csgv_status csgv_decode_bricks_noalloc(hipStream_t stream, const csgv_volume_info* vol, const void* d_container,
+                                       const uint32_t* d_brick_ids, const uint8_t* d_lods,
+                                       const uint64_t* d_out_offsets, uint32_t n, void* d_out, uint64_t out_capacity,
+                                       uint32_t* d_status, const csgv_decode_opts* opts);
+
+/*
  * Synchronise `stream` and report whether any of the n status words is
  * nonzero: CSGV_OK when all tasks succeeded, CSGV_ECORRUPT otherwise.
  */

@@ -64,6 +64,7 @@ _lib.csgv_last_error.restype = ctypes.c_char_p
 _lib.csgv_volume_parse.argtypes = [_P, _U64, ctypes.POINTER(VolumeInfo)]
 _lib.csgv_decode_bricks.argtypes = [_P, ctypes.POINTER(VolumeInfo), _P, _P, _P, _P, _U32, _P, _U64, _P,
                                     ctypes.POINTER(DecodeOpts)]
+_lib.csgv_decode_bricks_noalloc.argtypes = _lib.csgv_decode_bricks.argtypes
 _lib.csgv_check_status.argtypes = [_P, _U32, _P]
 _lib.csgv_plan_create.argtypes = [ctypes.POINTER(VolumeInfo), _U32, ctypes.POINTER(DecodeOpts), ctypes.POINTER(_P)]
 _lib.csgv_plan_launch.argtypes = [_P, _P, _P, _P, _P, _P, _U32, _P, _U64, _P]
@@ -91,7 +92,8 @@ _lib.csgv_encoder_finish.argtypes = [_P, ctypes.POINTER(_P), ctypes.POINTER(_U64
 _lib.csgv_encoder_destroy.argtypes = [_P]
 
 EXPORTED = [
-    "csgv_volume_parse", "csgv_decode_bricks", "csgv_check_status", "csgv_plan_create", "csgv_plan_launch",
+    "csgv_volume_parse", "csgv_decode_bricks", "csgv_decode_bricks_noalloc", "csgv_check_status", "csgv_plan_create",
+    "csgv_plan_launch",
     "csgv_plan_set_graph", "csgv_plan_set_timing", "csgv_plan_set_opts", "csgv_plan_get_opts",
     "csgv_plan_last_kernel_ms", "csgv_plan_destroy", "csgv_plan_autotune", "csgv_encode_bricks", "csgv_free_host", "csgv_last_error",
     "csgv_encoder_create", "csgv_encoder_add", "csgv_encoder_finish", "csgv_encoder_destroy",
@@ -147,6 +149,17 @@ def csgv_decode_bricks(stream, vol: VolumeInfo, d_container, d_brick_ids, d_lods
                                  _ptr(d_lods), _ptr(d_out_offsets), n, _ptr(d_out), out_capacity, _ptr(d_status),
                                  None if o is None else ctypes.byref(o))
     _check(rc, "csgv_decode_bricks")
+
+
+def csgv_decode_bricks_noalloc(stream, vol: VolumeInfo, d_container, d_brick_ids, d_lods, d_out_offsets, n: int,
+                               d_out, out_capacity: int, d_status=None, mode=None, wg_size=0, wgs_per_cu=0,
+                               sort_tasks=-1, bricks_per_wave=0, lds_slots=0):
+    """csgv_decode_bricks on the library's fixed scratch (no allocation; calls on one GPU must not overlap)."""
+    o = _opts(mode, wg_size, wgs_per_cu, sort_tasks, bricks_per_wave, lds_slots)
+    rc = _lib.csgv_decode_bricks_noalloc(_stream(stream), ctypes.byref(vol), _ptr(d_container), _ptr(d_brick_ids),
+                                         _ptr(d_lods), _ptr(d_out_offsets), n, _ptr(d_out), out_capacity,
+                                         _ptr(d_status), None if o is None else ctypes.byref(o))
+    _check(rc, "csgv_decode_bricks_noalloc")
 
 
 def csgv_check_status(d_status, n: int, stream=None) -> bool:

@@ -240,29 +240,14 @@ csgv_status csgv_volume_parse(const void* h_container, uint64_t bytes, csgv_volu
     return CSGV_OK;
 }
 
-csgv_status csgv_decode_bricks(hipStream_t stream, const csgv_volume_info* vol, const void* d_container,
-                               const uint32_t* d_brick_ids, const uint8_t* d_lods, const uint64_t* d_out_offsets,
-                               uint32_t n, void* d_out, uint64_t out_capacity, uint32_t* d_status,
-                               const csgv_decode_opts* opts) {
-    csgv_status st = check_task_args(vol, d_container, d_brick_ids, d_lods, n, d_out);
-    if (st != CSGV_OK || n == 0) return st;
-    if ((st = check_opts(opts)) != CSGV_OK) return st;
-    HIP_TRY(ensure_attrs());
-    const int mode = opts ? opts->mode : CSGV_MODE_PLAIN;
-    if (mode != CSGV_MODE_PLAIN && mode != CSGV_MODE_PERSISTENT) return fail(CSGV_EINVAL, "unknown mode %d", mode);
-    Params P = make_params(vol, d_container, d_brick_ids, d_lods, d_out_offsets, n, d_out, out_capacity, d_status);
-    if (opts && opts->lds_slots > 0) P.cap16 = std::max<uint32_t>((uint32_t)opts->lds_slots, kMinCap16);
-    const int wg = opts && opts->wg_size ? opts->wg_size : 256;
-    uint32_t grid = 1;
-    if (mode == CSGV_MODE_PERSISTENT) {
-        const int per_cu = opts && opts->wgs_per_cu > 0 ? opts->wgs_per_cu : resident_per_cu(wg, P.cap16);
-        grid = (uint32_t)std::min<uint64_t>((uint64_t)device_cus() * per_cu, n);
-    }
-    const uint64_t sb = P.scratch_stride * grid;
-    void* mem = nullptr;
-    HIP_TRY(hipMallocAsync(&mem, sb + aux_bytes(n), stream));
-    Bufs b;
-    carve((uint8_t*)mem, sb, n, &b);
+}  // extern "C"
+
+namespace {
+
+// Enqueue one call of csgv_decode_bricks on buffers b (scratch of `grid`
+// work-groups in persistent mode, of one in plain mode).
+csgv_status decode_on(hipStream_t stream, const csgv_volume_info* vol, Params P, const csgv_decode_opts* opts,
+                      int mode, int wg, uint32_t grid, const Bufs& b) {
     hipError_t e = hipSuccess;
     if (mode == CSGV_MODE_PERSISTENT) {
         const bool sort = opts ? opts->sort_tasks != 0 : true;
@@ -277,13 +262,56 @@ csgv_status csgv_decode_bricks(hipStream_t stream, const csgv_volume_info* vol, 
             P.dense_offs = b.dense;
             e = launch_dense_offsets(P, b.dense, stream);
         }
-        for (uint32_t j = 0; j < n && e == hipSuccess; ++j) {
+        for (uint32_t j = 0; j < P.n_tasks && e == hipSuccess; ++j) {
             P.task0 = j;
             e = launch_decode(P, wg, 1, stream);
         }
     }
-    hipError_t e2 = hipFreeAsync(mem, stream);
     if (e != hipSuccess) return fail(CSGV_EHIP, "decode launch: %s", hipGetErrorString(e));
+    return CSGV_OK;
+}
+
+// checks shared by both one-shot entry points; fills P, the mode and the shape
+csgv_status prepare_call(const csgv_volume_info* vol, const void* d_container, const uint32_t* d_brick_ids,
+                         const uint8_t* d_lods, const uint64_t* d_out_offsets, uint32_t n, void* d_out,
+                         uint64_t out_capacity, uint32_t* d_status, const csgv_decode_opts* opts, Params* P, int* mode,
+                         int* wg, int* per_cu) {
+    csgv_status st = check_task_args(vol, d_container, d_brick_ids, d_lods, n, d_out);
+    if (st != CSGV_OK || n == 0) return st;  // n = 0 enqueues nothing
+    if ((st = check_opts(opts)) != CSGV_OK) return st;
+    HIP_TRY(ensure_attrs());
+    *mode = opts ? opts->mode : CSGV_MODE_PLAIN;
+    if (*mode != CSGV_MODE_PLAIN && *mode != CSGV_MODE_PERSISTENT) return fail(CSGV_EINVAL, "unknown mode %d", *mode);
+    *P = make_params(vol, d_container, d_brick_ids, d_lods, d_out_offsets, n, d_out, out_capacity, d_status);
+    if (opts && opts->lds_slots > 0) P->cap16 = std::max<uint32_t>((uint32_t)opts->lds_slots, kMinCap16);
+    *wg = opts && opts->wg_size ? opts->wg_size : 256;
+    *per_cu = opts && opts->wgs_per_cu > 0 ? opts->wgs_per_cu : resident_per_cu(*wg, P->cap16);
+    return CSGV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+csgv_status csgv_decode_bricks(hipStream_t stream, const csgv_volume_info* vol, const void* d_container,
+                               const uint32_t* d_brick_ids, const uint8_t* d_lods, const uint64_t* d_out_offsets,
+                               uint32_t n, void* d_out, uint64_t out_capacity, uint32_t* d_status,
+                               const csgv_decode_opts* opts) {
+    Params P;
+    int mode, wg, per_cu;
+    csgv_status st = prepare_call(vol, d_container, d_brick_ids, d_lods, d_out_offsets, n, d_out, out_capacity,
+                                  d_status, opts, &P, &mode, &wg, &per_cu);
+    if (st != CSGV_OK || n == 0) return st;
+    uint32_t grid = 1;
+    if (mode == CSGV_MODE_PERSISTENT) grid = (uint32_t)std::min<uint64_t>((uint64_t)device_cus() * per_cu, n);
+    const uint64_t sb = P.scratch_stride * grid;
+    void* mem = nullptr;
+    HIP_TRY(hipMallocAsync(&mem, sb + aux_bytes(n), stream));
+    Bufs b;
+    carve((uint8_t*)mem, sb, n, &b);
+    st = decode_on(stream, vol, P, opts, mode, wg, grid, b);
+    hipError_t e2 = hipFreeAsync(mem, stream);
+    if (st != CSGV_OK) return st;
     if (e2 != hipSuccess) return fail(CSGV_EHIP, "hipFreeAsync: %s", hipGetErrorString(e2));
     return CSGV_OK;
 }
@@ -645,3 +673,65 @@ extern "C" csgv_status csgv_plan_autotune(csgv_plan* p, hipStream_t stream, cons
     if (report) *report = rep;
     return CSGV_OK;
 }
+
+// ------------------------------------------------- decode without allocating
+// Scratch of csgv_decode_bricks_noalloc: one array per GPU the library runs
+// on, held until the process ends.  Host code uses it only through the device
+// address hipGetSymbolAddress returns on each device (the array's name is a
+// host-side stand-in there).
+static __device__ __align__(256) uint8_t scratch[CSGV_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+uint8_t* g_noalloc_base[kMaxDevices] = {};
+
+// device address of this GPU's array, looked up once per device
+csgv_status noalloc_base(uint8_t** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(CSGV_EINVAL, "device %d beyond the supported %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_base[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_noalloc_base[dev] = (uint8_t*)p;
+    }
+    *out = g_noalloc_base[dev];
+    return CSGV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+csgv_status csgv_decode_bricks_noalloc(hipStream_t stream, const csgv_volume_info* vol, const void* d_container,
+                                       const uint32_t* d_brick_ids, const uint8_t* d_lods,
+                                       const uint64_t* d_out_offsets, uint32_t n, void* d_out, uint64_t out_capacity,
+                                       uint32_t* d_status, const csgv_decode_opts* opts) {
+    Params P;
+    int mode, wg, per_cu;
+    csgv_status st = prepare_call(vol, d_container, d_brick_ids, d_lods, d_out_offsets, n, d_out, out_capacity,
+                                  d_status, opts, &P, &mode, &wg, &per_cu);
+    if (st != CSGV_OK || n == 0) return st;
+    if (n > CSGV_NOALLOC_MAX_TASKS)
+        return fail(CSGV_EINVAL, "n = %u exceeds the %u tasks of the fixed scratch", n, (uint32_t)CSGV_NOALLOC_MAX_TASKS);
+    // per-task arrays for CSGV_NOALLOC_MAX_TASKS after the work-groups' scratch
+    const uint64_t aux = aux_bytes(CSGV_NOALLOC_MAX_TASKS);
+    const uint64_t sb = (CSGV_NOALLOC_SCRATCH_BYTES - aux) / 256 * 256;
+    const uint64_t fit = sb / P.scratch_stride;
+    if (fit == 0)
+        return fail(CSGV_EINVAL, "records of brick side 2^%u need %llu scratch bytes per work-group, more than the "
+                    "fixed scratch holds", P.max_log2b, (unsigned long long)P.scratch_stride);
+    uint32_t grid = 1;
+    if (mode == CSGV_MODE_PERSISTENT)
+        grid = (uint32_t)std::min<uint64_t>(std::min<uint64_t>((uint64_t)device_cus() * per_cu, n), fit);
+    uint8_t* base = nullptr;
+    if ((st = noalloc_base(&base)) != CSGV_OK) return st;
+    Bufs b;
+    carve(base, sb, CSGV_NOALLOC_MAX_TASKS, &b);
+    return decode_on(stream, vol, P, opts, mode, wg, grid, b);
+}
+
+}  // extern "C"
