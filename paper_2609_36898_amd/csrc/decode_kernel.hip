@@ -286,6 +286,9 @@ __device__ __forceinline__ void rans_decode(const Params& P, Shared& sh, const u
         uint32_t win2 = 128 + lane < gcount ? words[gbase + 128 + lane] : 0u;
         uint32_t gpos = 0, pend = 0;
         bool bad = false;
+        // the loop-carried state and window start from loads: let them land here,
+        // or every round would wait for all outstanding memory operations
+        __builtin_amdgcn_s_waitcnt(0);
         for (uint32_t r0 = 64 * g; r0 < nsym; r0 += W) {
             const uint32_t j = r0 + lane;
             const bool act = active && j < nsym;
@@ -455,19 +458,15 @@ __device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const 
     const uint32_t s0 = i ? sh.h.sym_end[i - 1] : 0u, s1 = sh.h.sym_end[i];
     uint32_t carry = 0, k_done = 0;
     bool bad = false;
-    uint32_t snext = 0;
-    if (s0 + tid < s1) {
-        const uint32_t j = s0 + tid;
-        snext = (nib[j >> 1] >> (4 * (j & 1))) & 15u;
-    }
+    // a pass's symbols are fetched one pass ahead, by every lane at a clamped
+    // index (no branch around the load, so nothing waits for it before use)
+    uint32_t nbyte = 0;
+    if (s0 < s1) nbyte = nib[min(s0 + tid, s1 - 1) >> 1];
     for (uint32_t c = s0; c < s1; c += NT) {
         const uint32_t j = c + tid;
         const bool valid = j < s1;
-        const uint32_t s = snext, pb = pbuf;
-        if (j + NT < s1) {
-            const uint32_t jn = j + NT;
-            snext = (nib[jn >> 1] >> (4 * (jn & 1))) & 15u;
-        }
+        const uint32_t s = (nbyte >> (4 * (j & 1))) & 15u, pb = pbuf;
+        nbyte = nib[min(j + NT, s1 - 1) >> 1];
         // delta entries come from registers: this lane's symbol and the next seven of
         // the wave; lanes near the wave's end complete them from the next wave's head
         const uint32_t n8 = next8(s);
