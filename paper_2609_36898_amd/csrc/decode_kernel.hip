@@ -72,8 +72,7 @@ struct TaskHdr {
 struct Shared {
     TaskHdr h;
     uint32_t err;
-    uint32_t pub[2][kMaxWaves];
-    uint32_t head[2][kMaxWaves];         // first 8 symbols of each wave's share of a pass
+    uint32_t pub[2][kMaxWaves][4];       // per pass and wave: run summary (f, n, a)
     uint32_t red[kMaxWaves + 2];
     uint32_t E[kEWords];                 // expansion bitmaps of levels 0..4
     uint16_t wpre[kEWords];              // exclusive popcount prefix of each bitmap word
@@ -148,30 +147,6 @@ constexpr int kDppWaveShr1 = 0x138;  // lane l takes lane l - 1
 constexpr int kDppBcast15 = 0x142;   // rows 1, 3 take lane 15 of the row before
 constexpr int kDppBcast31 = 0x143;   // rows 2, 3 take lane 31
 constexpr uint32_t kFnId = 2u;       // transfer function that keeps the state
-
-// Inclusive scan of 2-state transfer functions over the wavefront (lane 0
-// first): Hillis-Steele within rows of 16, then across rows by broadcasts.
-__device__ __forceinline__ uint32_t wave_scan_fn(uint32_t f) {
-    f = fn_then(dpp<kDppRowShr + 1>(kFnId, f), f);
-    f = fn_then(dpp<kDppRowShr + 2>(kFnId, f), f);
-    f = fn_then(dpp<kDppRowShr + 4>(kFnId, f), f);
-    f = fn_then(dpp<kDppRowShr + 8>(kFnId, f), f);
-    f = fn_then(dpp<kDppBcast15, 0xA>(kFnId, f), f);
-    f = fn_then(dpp<kDppBcast31, 0xC>(kFnId, f), f);
-    return f;
-}
-
-// The 4-bit symbols of this lane and the next seven lanes, low nibble first
-// (0 past lane 63).
-__device__ __forceinline__ uint32_t next8(uint32_t s) {
-    uint32_t r = s, v = s;
-#pragma unroll
-    for (int m = 1; m < 8; ++m) {
-        v = dpp<kDppWaveShl1>(0u, v);
-        r |= v << (4 * m);
-    }
-    return r;
-}
 
 // -------------------------------------------------------------- palette
 // Palette entry idx: staged in LDS (PAL_LDS) or read from the record.  LT is
@@ -437,7 +412,50 @@ __device__ __forceinline__ uint32_t level_setup(Shared& sh, const Store<V>& st, 
 }
 
 // ------------------------------------------------------------ level passes
+// 2-state automaton summary of a run of symbols for both entry states: f (bit
+// e = exit state when entered in state e), and per entry state the number of
+// operations (n) and of PALETTE_ADV operations (a), entry 0 in the low half,
+// entry 1 in the high half.
+struct RunSum {
+    uint32_t f, n, a;
+};
+constexpr uint32_t kHalf = 0xFFFFu;
+
+// the run `b` after the run `a`
+__device__ __forceinline__ RunSum run_then(const RunSum& x, const RunSum& y) {
+    const uint32_t s0 = 16u * (x.f & 1u), s1 = 16u * ((x.f >> 1) & 1u);
+    RunSum r;
+    r.f = fn_then(x.f, y.f);
+    r.n = x.n + ((y.n >> s0) & kHalf) + (((y.n >> s1) & kHalf) << 16);
+    r.a = x.a + ((y.a >> s0) & kHalf) + (((y.a >> s1) & kHalf) << 16);
+    return r;
+}
+
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ RunSum dpp_run(const RunSum& x) {
+    return RunSum{dpp<CTRL, ROWS>(kFnId, x.f), dpp<CTRL, ROWS>(0u, x.n), dpp<CTRL, ROWS>(0u, x.a)};
+}
+
+// inclusive scan of run summaries over the wavefront (lane 0 first)
+__device__ __forceinline__ RunSum wave_scan_run(RunSum x) {
+    x = run_then(dpp_run<kDppRowShr + 1>(x), x);
+    x = run_then(dpp_run<kDppRowShr + 2>(x), x);
+    x = run_then(dpp_run<kDppRowShr + 4>(x), x);
+    x = run_then(dpp_run<kDppRowShr + 8>(x), x);
+    x = run_then(dpp_run<kDppBcast15, 0xA>(x), x);
+    x = run_then(dpp_run<kDppBcast31, 0xC>(x), x);
+    return x;
+}
+
 // KIND 0: full level (i <= 4), 1: compact level 5, 2: level 6 in the output.
+//
+// A pass gives every thread R consecutive symbols (R = 1, 2, 4 or 8 per level:
+// the fewest that still fill one pass, so small levels do not serialise).
+// Each thread summarises its R symbols for both automaton entry states; a
+// wavefront scan and a scan of the waves' totals give each thread its entry
+// state, its first operation rank and its first palette (ADV) rank; then each
+// thread decodes its own operations in order.  References to nodes decoded in
+// the same pass are resolved after it.
 template <int NT, int KIND, typename V, bool BIG, bool LIST_LDS>
 __device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const Store<V>& st, const uint8_t* nib, uint32_t i,
                              uint32_t expected, uint32_t& adv_done, uint32_t& pbuf) {
@@ -456,180 +474,212 @@ __device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const 
     uint32_t* const Ei_g = KIND == 1 && i < t ? st.E5 : nullptr;
     const uint32_t mx = 0x09249249u & (nodes - 1u), my = mx << 1, mz = mx << 2;
     const uint32_t s0 = i ? sh.h.sym_end[i - 1] : 0u, s1 = sh.h.sym_end[i];
+    const uint32_t* const nib32 = (const uint32_t*)nib;
+    const uint32_t n_sym = s1 - s0;
+    const uint32_t lr = n_sym <= NT ? 0u : n_sym <= 2u * NT ? 1u : n_sym <= 4u * NT ? 2u : 3u;  // log2 R
+    const uint32_t g_first = s0 >> lr, g_last = n_sym ? (s1 - 1u) >> lr : 0u;
+    const uint32_t n_groups = n_sym ? g_last - g_first + 1u : 0u;
+    const uint32_t w_last = n_sym ? (s1 - 1u) >> 3 : 0u;  // last word holding a symbol of the level
+    // slot of the operation of rank k whose node is p
+    auto slot_of = [&](uint32_t k, uint32_t p) -> uint32_t { return KIND == 0 ? p : KIND == 1 ? k : vox6(p); };
+    auto parent_of = [&](uint32_t k) -> uint32_t {
+        return i ? (LIST_LDS ? (uint32_t)st.list_l[k >> 3] : (uint32_t)st.list_g[k >> 3]) : 0u;
+    };
+    auto read_slot = [&](uint32_t x) -> uint32_t {
+        return KIND == 0 ? (uint32_t)full_i[x] : KIND == 1 ? (uint32_t)st.c5[x] : st.out6[(uint64_t)x * st.lb4];
+    };
+    auto write_slot = [&](uint32_t x, uint32_t v) {
+        if (KIND == 0) full_i[x] = (V)v;
+        else if (KIND == 1) st.c5[x] = (V)v;
+        else st.out6[(uint64_t)x * st.lb4] = v;
+    };
     uint32_t carry = 0, k_done = 0;
     bool bad = false;
-    // a pass's symbols are fetched one pass ahead, by every lane at a clamped
-    // index (no branch around the load, so nothing waits for it before use)
-    uint32_t nbyte = 0;
-    if (s0 < s1) nbyte = nib[min(s0 + tid, s1 - 1) >> 1];
-    for (uint32_t c = s0; c < s1; c += NT) {
-        const uint32_t j = c + tid;
-        const bool valid = j < s1;
-        const uint32_t s = (nbyte >> (4 * (j & 1))) & 15u, pb = pbuf;
-        nbyte = nib[min(j + NT, s1 - 1) >> 1];
-        // delta entries come from registers: this lane's symbol and the next seven of
-        // the wave; lanes near the wave's end complete them from the next wave's head
-        const uint32_t n8 = next8(s);
-        if (lane == 0) sh.head[pb][wave] = n8;
-        // classification for both entry states
-        const uint64_t m_valid = __ballot(valid);
-        const uint64_t m_cand = __ballot(valid && (s & 7u) == kDelta);
-        const uint64_t m_adv = __ballot(valid && (s & 7u) == kAdv);
-        uint64_t ops0, ops1;
-        uint32_t x0, x1;
-        if (m_cand == 0) {
-            ops0 = m_valid;
-            x0 = 0;
-            const uint64_t m_end = m_valid & ~__ballot(valid && (s & 8u));
-            if (m_end) {
-                const uint32_t f = (uint32_t)__builtin_ctzll(m_end);
-                const uint64_t upto = f >= 63 ? ~0ull : ((2ull << f) - 1ull);
-                ops1 = m_valid & ~upto;
-                x1 = 0;
-            } else {
-                ops1 = 0;
-                x1 = 1;
-            }
-        } else {
-            const uint32_t f = valid ? (((s & 7u) == kDelta ? 1u : 0u) | (((s >> 3) & 1u) << 1)) : 2u;
-            const uint32_t incl = wave_scan_fn(f);
-            const uint32_t excl = dpp<kDppWaveShr1>(kFnId, incl);
-            ops0 = __ballot(valid && !(excl & 1u));
-            ops1 = __ballot(valid && !((excl >> 1) & 1u));
-            const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-            x0 = tot & 1u;
-            x1 = (tot >> 1) & 1u;
+    // each thread reads the two words holding its group of R symbols and what
+    // follows it (delta entries), one pass ahead, at clamped indices: no branch
+    // around the loads, so nothing waits for them before their use
+    uint32_t nlo = 0, nhi = 0;
+    if (n_groups) {
+        const uint32_t w = ((g_first + tid) << lr) >> 3;
+        nlo = nib32[min(w, w_last)];
+        nhi = nib32[min(w + 1u, w_last)];
+    }
+    for (uint32_t pg = 0; pg < n_groups; pg += NT) {
+        const uint32_t g = g_first + pg + tid, j0 = g << lr, pb = pbuf;
+        // symbols j0, j0 + 1, ... from bit 0 on (16 - (j0 & 7) of them)
+        const uint64_t win = ((((uint64_t)nhi) << 32) | nlo) >> (4u * (j0 & 7u));
+        const uint32_t word = (uint32_t)win, avail = 16u - (j0 & 7u);
+        {
+            const uint32_t w = ((g + NT) << lr) >> 3;
+            nlo = nib32[min(w, w_last)];
+            nhi = nib32[min(w + 1u, w_last)];
         }
-        if (lane == 0) {
-            sh.pub[pb][wave] = (uint32_t)__popcll(ops0) | ((uint32_t)__popcll(ops1) << 7) |
-                                 ((uint32_t)__popcll(ops0 & m_adv) << 14) | ((uint32_t)__popcll(ops1 & m_adv) << 21) |
-                                 (x0 << 28) | (x1 << 29);
+        // symbols of this group that belong to the level
+        uint32_t vm = 0;
+        if (g <= g_last) {
+            const uint32_t lo = s0 > j0 ? s0 - j0 : 0u, hi = min(s1 - j0, 1u << lr);
+            vm = ((1u << hi) - 1u) & ~((1u << lo) - 1u);
+        }
+        RunSum x{0u, 0u, 0u};
+        {
+            uint32_t e0 = 0, e1 = 1, n0 = 0, n1 = 0, a0 = 0, a1 = 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint32_t sym = (word >> (4 * q)) & 15u, vq = (vm >> q) & 1u;
+                const uint32_t isd = (sym & 7u) == kDelta, isa = (sym & 7u) == kAdv, cont = sym >> 3;
+                const uint32_t op0 = vq & (e0 ^ 1u), op1 = vq & (e1 ^ 1u);
+                n0 += op0;
+                n1 += op1;
+                a0 += op0 & isa;
+                a1 += op1 & isa;
+                e0 = vq ? (e0 ? cont : isd) : e0;
+                e1 = vq ? (e1 ? cont : isd) : e1;
+            }
+            x = RunSum{e0 | (e1 << 1), n0 | (n1 << 16), a0 | (a1 << 16)};
+        }
+        const RunSum incl = wave_scan_run(x);
+        const RunSum excl = dpp_run<kDppWaveShr1>(incl);
+        if (lane == 63) {
+            uint32_t* pub = sh.pub[pb][wave];
+            pub[0] = incl.f;
+            pub[1] = incl.n;
+            pub[2] = incl.a;
         }
         __syncthreads();
-        // fold the waves' summaries: this wave's entry state, op base, ADV base; pass totals
-        uint32_t e = carry, kb = k_done, ab = adv_done, my_e = 0, my_kb = 0, my_ab = 0;
-#pragma unroll
-        for (uint32_t w = 0; w < NW; ++w) {
-            if (w == wave) {
-                my_e = e;
-                my_kb = kb;
-                my_ab = ab;
-            }
-            const uint32_t p = sh.pub[pb][w];
-            const uint32_t q = e ? (p >> 7) : p;
-            kb += q & 127u;
-            ab += (q >> 14) & 127u;
-            e = (p >> (28 + e)) & 1u;
-        }
+        // the waves' totals, scanned over the first NW lanes (one row of 16):
+        // this wave's entry state, operation base and ADV base, and the pass totals
+        RunSum wt{kFnId, 0u, 0u};
+        if (lane < NW) wt = RunSum{sh.pub[pb][lane][0], sh.pub[pb][lane][1], sh.pub[pb][lane][2]};
+        wt = run_then(dpp_run<kDppRowShr + 1>(wt), wt);
+        wt = run_then(dpp_run<kDppRowShr + 2>(wt), wt);
+        wt = run_then(dpp_run<kDppRowShr + 4>(wt), wt);
+        wt = run_then(dpp_run<kDppRowShr + 8>(wt), wt);
+        const RunSum we = dpp_run<kDppRowShr + 1>(wt);
+        const uint32_t wf = (uint32_t)__builtin_amdgcn_readlane((int)we.f, (int)wave);
+        const uint32_t wn = (uint32_t)__builtin_amdgcn_readlane((int)we.n, (int)wave);
+        const uint32_t wa = (uint32_t)__builtin_amdgcn_readlane((int)we.a, (int)wave);
+        const uint32_t tf = (uint32_t)__builtin_amdgcn_readlane((int)wt.f, (int)(NW - 1));
+        const uint32_t tn = (uint32_t)__builtin_amdgcn_readlane((int)wt.n, (int)(NW - 1));
+        const uint32_t ta = (uint32_t)__builtin_amdgcn_readlane((int)wt.a, (int)(NW - 1));
+        const uint32_t my_e = (wf >> carry) & 1u;
+        const uint32_t my_kb = k_done + ((wn >> (16 * carry)) & kHalf);
+        const uint32_t my_ab = adv_done + ((wa >> (16 * carry)) & kHalf);
         const uint32_t k0 = k_done;
-        carry = e;
-        k_done = kb;
-        adv_done = ab;
+        k_done += (tn >> (16 * carry)) & kHalf;
+        adv_done += (ta >> (16 * carry)) & kHalf;
+        carry = (tf >> carry) & 1u;
         pbuf ^= 1u;
-        const uint64_t my_ops = my_e ? ops1 : ops0;
-        uint32_t myidx = 0, myval = 0;
-        bool is_ref = false;
-        if ((my_ops >> lane) & 1u) {
-            const uint32_t k = my_kb + mbcnt(my_ops);
-            const uint32_t a = my_ab + mbcnt(my_ops & m_adv);
-            const uint32_t op = s & 7u;
+        uint32_t ls = (excl.f >> my_e) & 1u;
+        uint32_t k = my_kb + ((excl.n >> (16 * my_e)) & kHalf);
+        uint32_t a = my_ab + ((excl.a >> (16 * my_e)) & kHalf);
+        const uint32_t k_first = k;
+        uint32_t opm = 0, refm = 0;
+        for (uint32_t q = 0; q < (1u << lr); ++q) {
+            if (!((vm >> q) & 1u)) continue;
+            const uint32_t sym = (word >> (4 * q)) & 15u;
+            if (ls) {  // a delta entry, read by its operation
+                ls = sym >> 3;
+                continue;
+            }
+            const uint32_t op = sym & 7u;
+            ls = op == kDelta;
+            opm |= 1u << q;
             if (k >= expected) {
                 bad = true;
-            } else {
-                const uint32_t r = k >> 3;
-                const uint32_t pn = i ? (LIST_LDS ? (uint32_t)st.list_l[r] : (uint32_t)st.list_g[r]) : 0u;
-                const uint32_t p = i ? ((pn << 3) | (k & 7u)) : 0u;
-                myidx = KIND == 0 ? p : KIND == 1 ? k : vox6(p);
-                uint32_t v = FIN;
-                if (op == kParent) {
-                    if (i == 0) bad = true;
-                    else if (KIND == 2) v = (st.pval_g[r] & VIDX) | FIN;
-                    else v = full_p[pn];
-                } else if (op <= kNZ) {
-                    const uint32_t am = op == kNX ? mx : op == kNY ? my : mz;
-                    if (!(p & am)) {
-                        bad = true;
-                    } else {
-                        const uint32_t tn = (((p & am) - 1u) & am) | (p & ~am);
-                        if (KIND == 0) {
-                            // implied targets hold their parent's value, explicit ones of earlier
-                            // passes their final value, those of this pass "not yet" or a reference
-                            v = full_i[tn];
-                            if (v == (uint32_t)Slot<V>::kNotYet) v = tn;
-                        } else {
-                            const uint32_t tq = tn >> 3;
-                            if (KIND == 1 ? !st.ebit(4, tq) : !st.ebit5(tq)) {
-                                v = KIND == 1 ? (uint32_t)full_p[tq] : ((st.value5(tq) & VIDX) | FIN);
-                            } else {
-                                const uint32_t kt = 8 * (KIND == 1 ? st.rank(4, tq) : st.rank5(tq)) + (tn & 7u);
-                                const uint32_t ti = KIND == 1 ? kt : vox6(tn);
-                                if (kt < k0) v = KIND == 1 ? (uint32_t)st.c5[ti] : st.out6[(uint64_t)ti * st.lb4];
-                                else v = ti;
-                            }
-                        }
-                        is_ref = !(v & FIN);
-                    }
-                } else if (op == kAdv) {
-                    if (a >= pc) bad = true;
-                    else v = FIN | a;
-                } else if (op == kLast) {
-                    if (a == 0) bad = true;
-                    else v = FIN | (a - 1u);
-                } else if (op == kDelta) {
-                    // entries j+1 .. j+lim-1 are in w8; later ones (past the pass) are read
-                    uint32_t w8 = n8, lim = 8;
-                    if (lane > 56u) {
-                        const uint32_t sft = 4u * (64u - lane);
-                        if (wave + 1 < NW) w8 = (w8 & ((1u << sft) - 1u)) | (sh.head[pb][wave + 1] << sft);
-                        else lim = 64u - lane;
-                    }
-                    uint32_t d = 0, m = 1, en = 8;
-                    while (en & 8u) {
-                        const uint32_t jj = j + m;
-                        if (jj >= s1) {
-                            bad = true;
-                            break;
-                        }
-                        en = m < lim ? (w8 >> (4 * m)) & 15u : (nib[jj >> 1] >> (4 * (jj & 1))) & 15u;
-                        d = d >= (1u << 29) ? 0xFFFFFFFFu : ((d << 3) | (en & 7u));
-                        ++m;
-                    }
-                    if (d == 0 || d > a) bad = true;
-                    else v = FIN | (a - d);
-                } else {
-                    bad = true;
-                }
-                if (bad) {
-                    v = FIN;
-                    is_ref = false;
-                }
-                myval = v;
-                // written even after an error, so that a later lookup never meets an unset slot
-                if (KIND == 0) full_i[myidx] = (V)v;
-                else if (KIND == 1) st.c5[myidx] = (V)v;
-                else st.out6[(uint64_t)myidx * st.lb4] = v;
-                if (!(s & 8u)) {
-                    if (Ei_l) atomicOr(Ei_l + (p >> 5), 1u << (p & 31));
-                    if (Ei_g) atomicOr(Ei_g + (p >> 5), 1u << (p & 31));
-                }
+                ++k;
+                continue;
             }
+            const uint32_t pn = parent_of(k);
+            const uint32_t p = i ? ((pn << 3) | (k & 7u)) : 0u;
+            uint32_t v = FIN;
+            bool is_ref = false, err = false;
+            if (op == kParent) {
+                if (i == 0) err = true;
+                else if (KIND == 2) v = (st.pval_g[k >> 3] & VIDX) | FIN;
+                else v = full_p[pn];
+            } else if (op <= kNZ) {
+                const uint32_t am = op == kNX ? mx : op == kNY ? my : mz;
+                if (!(p & am)) {
+                    err = true;
+                } else {
+                    const uint32_t tn = (((p & am) - 1u) & am) | (p & ~am);
+                    if (KIND == 0) {
+                        // implied targets hold their parent's value, explicit ones of earlier
+                        // passes their final value, those of this pass "not yet" or a reference
+                        v = full_i[tn];
+                        if (v == (uint32_t)Slot<V>::kNotYet) v = tn;
+                    } else {
+                        const uint32_t tq = tn >> 3;
+                        if (KIND == 1 ? !st.ebit(4, tq) : !st.ebit5(tq)) {
+                            v = KIND == 1 ? (uint32_t)full_p[tq] : ((st.value5(tq) & VIDX) | FIN);
+                        } else {
+                            const uint32_t kt = 8 * (KIND == 1 ? st.rank(4, tq) : st.rank5(tq)) + (tn & 7u);
+                            const uint32_t ti = KIND == 1 ? kt : vox6(tn);
+                            v = kt < k0 ? read_slot(ti) : ti;
+                        }
+                    }
+                    is_ref = !(v & FIN);
+                }
+            } else if (op == kAdv) {
+                if (a >= pc) err = true;
+                else v = FIN | a;
+            } else if (op == kLast) {
+                if (a == 0) err = true;
+                else v = FIN | (a - 1u);
+            } else if (op == kDelta) {
+                // entries follow the operation: in the window, else (long chains) in memory
+                uint32_t d = 0, m = q + 1u, en = 8;
+                while (en & 8u) {
+                    const uint32_t jj = j0 + m;
+                    if (jj >= s1) {
+                        err = true;
+                        break;
+                    }
+                    en = m < avail ? (uint32_t)(win >> (4 * m)) & 15u : (nib[jj >> 1] >> (4 * (jj & 1))) & 15u;
+                    d = d >= (1u << 29) ? 0xFFFFFFFFu : ((d << 3) | (en & 7u));
+                    ++m;
+                }
+                if (!err) {
+                    if (d == 0 || d > a) err = true;
+                    else v = FIN | (a - d);
+                }
+            } else {
+                err = true;
+            }
+            if (err) {
+                bad = true;
+                v = FIN;
+                is_ref = false;
+            }
+            // written even after an error, so that a later lookup never meets an unset slot
+            write_slot(slot_of(k, p), v);
+            refm |= (is_ref ? 1u : 0u) << q;
+            if (!(sym & 8u)) {
+                if (Ei_l) atomicOr(Ei_l + (p >> 5), 1u << (p & 31));
+                if (Ei_g) atomicOr(Ei_g + (p >> 5), 1u << (p & 31));
+            }
+            a += op == kAdv;
+            ++k;
         }
         __syncthreads();
-        // references within the pass: chase to a final value
-        if (is_ref) {
+        // references within the pass: chase to a final value (targets precede
+        // their sources, so every chain ends within the pass's operations)
+        for (uint32_t m = refm; m; m &= m - 1u) {
+            const uint32_t q = (uint32_t)__builtin_ctz(m);
+            const uint32_t kq = k_first + (uint32_t)__popc(opm & ((1u << q) - 1u));
+            const uint32_t pq = i ? ((parent_of(kq) << 3) | (kq & 7u)) : 0u;
+            const uint32_t me = slot_of(kq, pq);
             const uint32_t lim = KIND == 0 ? nodes : KIND == 1 ? k_done : (1u << 18);
-            uint32_t v = myval, it = 0;
+            uint32_t v = read_slot(me), it = 0;
             while (!(v & FIN)) {
-                if ((v & IDX) >= lim || ++it > NT) {
+                if ((v & IDX) >= lim || ++it > 8 * NT) {
                     bad = true;
                     v = FIN;
                     break;
                 }
-                v = KIND == 0 ? (uint32_t)full_i[v] : KIND == 1 ? (uint32_t)st.c5[v] : st.out6[(uint64_t)v * st.lb4];
+                v = read_slot(v & IDX);
             }
-            if (KIND == 0) full_i[myidx] = (V)v;
-            else if (KIND == 1) st.c5[myidx] = (V)v;
-            else st.out6[(uint64_t)myidx * st.lb4] = v;
+            write_slot(me, v);
         }
     }
     if (bad) atomicOr(&sh.err, 1u);
@@ -823,17 +873,22 @@ __device__ __forceinline__ void decode_task(const Params& P, Shared& sh, uint16_
         if (h.status == kTaskCorrupt && h.write_ok) zero_output<NT>(P, h);
         return;
     }
-    const uint8_t* nib;
+    // the symbols (4 bits each) go to the work-group's scratch, where the level
+    // passes read them as aligned 32-bit words
+    uint8_t* const nib = scratch + kScrSym;
     if (h.coder == kRaw4) {
-        nib = P.vol + h.pay_off;
+        const uint32_t bytes = (h.nsym + 1u) / 2u, words = bytes / 4u;
+        const uint32_t* src = (const uint32_t*)(P.vol + h.pay_off);
+        for (uint32_t w = threadIdx.x; w < words; w += NT) ((uint32_t*)nib)[w] = src[w];
+        for (uint32_t b = 4u * words + threadIdx.x; b < bytes; b += NT) nib[b] = P.vol[h.pay_off + b];
+        __syncthreads();
     } else {
         // the rANS table borrows the slot area (at least 16 KiB) until the levels start
         uint32_t* tab = (uint32_t*)slots_lds;
         const uint4* src = (const uint4*)P.rans_tab;
         for (uint32_t w = threadIdx.x; w < kRansM / 4; w += NT) ((uint4*)tab)[w] = src[w];
         __syncthreads();
-        rans_decode<NT>(P, sh, tab, scratch + kScrSym);
-        nib = scratch + kScrSym;
+        rans_decode<NT>(P, sh, tab, nib);
         __syncthreads();
     }
     if (!sh.err) {
