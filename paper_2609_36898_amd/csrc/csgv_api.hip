@@ -283,7 +283,7 @@ csgv_status prepare_call(const csgv_volume_info* vol, const void* d_container, c
     *mode = opts ? opts->mode : CSGV_MODE_PLAIN;
     if (*mode != CSGV_MODE_PLAIN && *mode != CSGV_MODE_PERSISTENT) return fail(CSGV_EINVAL, "unknown mode %d", *mode);
     *P = make_params(vol, d_container, d_brick_ids, d_lods, d_out_offsets, n, d_out, out_capacity, d_status);
-    if (opts && opts->lds_slots > 0) P->cap16 = std::max<uint32_t>((uint32_t)opts->lds_slots, kMinCap16);
+    if (opts && opts->lds_slots > 0) P->cap16 = std::max<uint32_t>((uint32_t)opts->lds_slots, kMinCap16) & ~7u;
     *wg = opts && opts->wg_size ? opts->wg_size : 256;
     *per_cu = opts && opts->wgs_per_cu > 0 ? opts->wgs_per_cu : resident_per_cu(*wg, P->cap16);
     return CSGV_OK;
@@ -368,7 +368,7 @@ uint32_t plan_grid(const csgv_plan* p, uint32_t n) {
 
 csgv_status plan_enqueue(csgv_plan* p, hipStream_t s, const Params& P0, bool with_events) {
     Params P = P0;
-    P.cap16 = std::max<uint32_t>((uint32_t)p->opts.lds_slots, kMinCap16);
+    P.cap16 = std::max<uint32_t>((uint32_t)p->opts.lds_slots, kMinCap16) & ~7u;
     hipError_t e = enqueue_persistent(P, p->b, &p->vol, p->opts.wg_size, plan_grid(p, P.n_tasks),
                                       p->opts.sort_tasks != 0, s, with_events ? p->ev0 : nullptr,
                                       with_events ? p->ev1 : nullptr);

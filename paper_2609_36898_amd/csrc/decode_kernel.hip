@@ -80,6 +80,9 @@ struct Shared {
     alignas(16) uint8_t U[kUBytes];      // parent list of the level being decoded | staged palette
 };
 static_assert(sizeof(Shared) % 16 == 0, "the slot area follows Shared 16-byte aligned");
+static_assert(offsetof(Shared, U) == offsetof(Shared, G) + sizeof(Shared::G) &&
+                  offsetof(Shared, U) + sizeof(Shared::U) == sizeof(Shared),
+              "grids, parent list and slot area form one range (rANS staging)");
 
 // ------------------------------------------------------ wave/block helpers
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
@@ -305,6 +308,69 @@ __device__ __forceinline__ void rans_decode(const Params& P, Shared& sh, const u
         }
         if (__ballot(bad) && lane == 0) atomicOr(&sh.err, 1u);
     }
+}
+
+// The same decode with the record's words and the decoded symbols staged in
+// LDS (`stage`, the level grids and slot area, idle until the levels start):
+// a lane that renormalises reads its word from LDS, and the symbols reach the
+// work-group's scratch in one coalesced copy at the end, so no round waits on
+// a global store.  The caller checks that words and symbols fit.
+template <int NT>
+__device__ __forceinline__ void rans_decode_lds(const Params& P, Shared& sh, const uint32_t* tab, uint8_t* stage,
+                                                uint8_t* nib) {
+    const TaskHdr& h = sh.h;
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    const uint32_t W = 1u << h.log2W, G = (W + 63) / 64, lanes = W < 64 ? W : 64;
+    const uint32_t nsym = h.nsym, tw = h.gstart[G - 1] + h.gw[G - 1];
+    uint16_t* const wl = (uint16_t*)stage;
+    uint8_t* const nl = stage + ((2u * tw + 15u) & ~15u);
+    const uint16_t* const wg = (const uint16_t*)(P.vol + h.pay_off);
+    for (uint32_t q = tid; q < tw / 2u; q += NT) ((uint32_t*)wl)[q] = ((const uint32_t*)wg)[q];
+    if ((tw & 1u) && tid == 0) wl[tw - 1u] = wg[tw - 1u];
+    __syncthreads();
+    const uint32_t* states = (const uint32_t*)(P.vol + h.states_off);
+    for (uint32_t g = wave; g < G; g += NT / 64) {
+        const bool active = lane < lanes;
+        const uint32_t gcount = h.gw[g], gbase = h.gstart[g];
+        uint32_t x = active ? states[64 * g + lane] : 0u;
+        uint32_t gpos = 0, pend = 0;
+        bool bad = false;
+        __builtin_amdgcn_s_waitcnt(0);
+        for (uint32_t r0 = 64 * g; r0 < nsym; r0 += W) {
+            const uint32_t j = r0 + lane;
+            const bool act = active && j < nsym;
+            uint32_t s = 0;
+            if (act) {
+                const uint32_t e = tab[x & (kRansM - 1)];
+                s = e & 15u;
+                x = ((e >> 4) & 0x1FFFu) * (x >> kRansBits) + (e >> 17);
+            }
+            const bool need = act && x < kRansL;
+            const uint64_t m = __ballot(need);
+            if (need) {
+                const uint32_t widx = gpos + mbcnt(m);
+                if (widx >= gcount) bad = true;
+                else x = (x << 16) | wl[gbase + widx];
+            }
+            gpos += (uint32_t)__popcll(m);
+            // two consecutive symbols per byte
+            if (W >= 2) {
+                const uint32_t hi = dpp<0xB1>(0u, s);  // quad_perm [1,0,3,2]: the pair partner
+                if (act && !(lane & 1)) nl[j >> 1] = (uint8_t)(s | (j + 1 < nsym ? hi << 4 : 0u));
+            } else if (lane == 0) {
+                if (!(j & 1)) {
+                    pend = s;
+                    if (j + 1 == nsym) nl[j >> 1] = (uint8_t)pend;
+                } else {
+                    nl[j >> 1] = (uint8_t)(pend | (s << 4));
+                }
+            }
+        }
+        if (__ballot(bad) && lane == 0) atomicOr(&sh.err, 1u);
+    }
+    __syncthreads();
+    const uint32_t nw = ((nsym + 1u) / 2u + 3u) / 4u;
+    for (uint32_t q = tid; q < nw; q += NT) ((uint32_t*)nib)[q] = ((const uint32_t*)nl)[q];
 }
 
 // ------------------------------------------------------------ level store
@@ -883,12 +949,19 @@ __device__ __forceinline__ void decode_task(const Params& P, Shared& sh, uint16_
         for (uint32_t b = 4u * words + threadIdx.x; b < bytes; b += NT) nib[b] = P.vol[h.pay_off + b];
         __syncthreads();
     } else {
-        // the rANS table borrows the slot area (at least 16 KiB) until the levels start
-        uint32_t* tab = (uint32_t*)slots_lds;
+        // the rANS table borrows the last 16 KiB of the slot area until the levels
+        // start; the grids, parent list and the rest of the slot area before it can
+        // stage the record's words and the decoded symbols
+        uint8_t* const stage = (uint8_t*)sh.G;
+        const uint32_t stage_bytes = (uint32_t)(sizeof(sh.G) + sizeof(sh.U)) + 2u * P.cap16 - 4u * kRansM;
+        uint32_t* tab = (uint32_t*)(stage + stage_bytes);
         const uint4* src = (const uint4*)P.rans_tab;
         for (uint32_t w = threadIdx.x; w < kRansM / 4; w += NT) ((uint4*)tab)[w] = src[w];
         __syncthreads();
-        rans_decode<NT>(P, sh, tab, nib);
+        const uint32_t G = ((1u << h.log2W) + 63u) / 64u, tw = h.gstart[G - 1] + h.gw[G - 1];
+        const uint32_t need = ((2u * tw + 15u) & ~15u) + ((h.nsym + 1u) / 2u + 3u) / 4u * 4u;
+        if (need <= stage_bytes) rans_decode_lds<NT>(P, sh, tab, stage, nib);
+        else rans_decode<NT>(P, sh, tab, nib);
         __syncthreads();
     }
     if (!sh.err) {

@@ -103,6 +103,7 @@ public:
     // while anything is waiting, queued or in flight.
     bool step(double now) {
         // pairs of requests completed in the previous step: the caller has seen them
+        prefetch_keys(to_unpin_);
         for (uint64_t k : to_unpin_) unpin(k);
         to_unpin_.clear();
         for (int s = 0; s < (int)batches_.size(); ++s)
@@ -300,8 +301,17 @@ private:
         }
     }
 
+    // the table slots, then the entries, of a run of keys: issued together so
+    // that the walks that follow find them in cache
+    void prefetch_keys(const std::vector<uint64_t>& keys) {
+        for (uint64_t k : keys) __builtin_prefetch(&slot_[k]);
+        for (uint64_t k : keys)
+            if (const uint32_t s = slot_[k]) __builtin_prefetch(&ent_[s - 1]);
+    }
+
     bool admit(Req& r, double now) {
         created_.clear();
+        prefetch_keys(r.keys);
         for (size_t j = 0; j < r.keys.size(); ++j) {
             const uint64_t k = r.keys[j];
             if (const uint32_t s = slot_[k]) {
