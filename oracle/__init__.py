@@ -49,6 +49,10 @@ def _load():
                                          ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(U64)]
     lib.oracle_free.argtypes = [P]
     lib.oracle_decode_tasks.argtypes = [P, U64, P, P, P, U32, P, U64, P, I]
+    lib.oracle_decode_tasks_paletted.argtypes = [P, U64, P, P, P, U32, P, U64, P, I, I]
+    lib.oracle_pack_indices.argtypes = [P, U64, I, P]
+    lib.oracle_record_palette.argtypes = [P, U64, U32, P, U32]
+    lib.oracle_record_palette.restype = ctypes.c_int64
     lib.oracle_record_symbols.argtypes = [P, U64, U32, P, U32, P, P]
     lib.oracle_record_symbols.restype = ctypes.c_int64
     _lib = lib
@@ -173,6 +177,51 @@ def decode_tasks(container: bytes, ids, lods, out_offsets, out_cap: int, label_b
     if rc != 0:
         raise ValueError("unusable container header")
     return out, status[:len(ids)]
+
+
+def pack_indices(idx, bits: int) -> np.ndarray:
+    """Palette indices packed floor(32/bits) to a 32-bit word (cache paletting)."""
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.uint32))
+    e = 32 // bits
+    out = np.empty(max((len(idx) + e - 1) // e, 1), dtype=np.uint32)
+    _load().oracle_pack_indices(idx.ctypes.data, len(idx), bits, out.ctypes.data)
+    return out[:(len(idx) + e - 1) // e]
+
+
+def paletted_words(n_voxels, bits: int):
+    """32-bit words one task's packed indices occupy."""
+    e = 32 // bits
+    return (np.asarray(n_voxels, dtype=np.int64) + e - 1) // e
+
+
+def decode_tasks_paletted(container: bytes, ids, lods, word_offsets, out_words: int, bits: int,
+                          nthreads: int = 1, out: np.ndarray | None = None):
+    """Decode tasks to cache-paletted form (packed palette indices, bits each,
+    floor(32/bits) per 32-bit word) at word offsets; returns (words, status)."""
+    lib = _load()
+    ids = np.ascontiguousarray(np.asarray(ids, dtype=np.uint32))
+    lods = np.ascontiguousarray(np.asarray(lods, dtype=np.uint8))
+    offs = np.ascontiguousarray(np.asarray(word_offsets, dtype=np.uint64))
+    if out is None:
+        out = np.full(max(out_words, 1), 0xA5A5A5A5, dtype=np.uint32)
+    status = np.zeros(max(len(ids), 1), dtype=np.uint32)
+    buf = np.frombuffer(container, dtype=np.uint8)
+    rc = lib.oracle_decode_tasks_paletted(buf.ctypes.data, len(container), ids.ctypes.data, lods.ctypes.data,
+                                          offs.ctypes.data, len(ids), out.ctypes.data, out_words,
+                                          status.ctypes.data, bits, nthreads)
+    if rc != 0:
+        raise ValueError("unusable container header or bits")
+    return out, status[:len(ids)]
+
+
+def record_palette(container: bytes, brick_id: int) -> np.ndarray:
+    """Palette entries of one record (u64 values of the volume's label width)."""
+    buf = np.frombuffer(container, dtype=np.uint8)
+    out = np.zeros(1 << 18, dtype=np.uint64)
+    n = _load().oracle_record_palette(buf.ctypes.data, len(container), brick_id, out.ctypes.data, len(out))
+    if n < 0:
+        raise ValueError("unreadable record")
+    return out[:n].copy()
 
 
 def record_symbols(container: bytes, brick_id: int):

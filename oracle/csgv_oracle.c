@@ -589,7 +589,8 @@ typedef struct {
  *   record offsets ordered, in the buffer, 8-aligned, >= 8 bytes   else CORRUPT (no write)
  *   log2b in [1, 6]                                    else CORRUPT (no write)
  *   lod <= log2b                                       else INVALID
- *   output range fits                                  else INVALID
+ *   output range fits (labels, or 32-bit words of       else INVALID
+ *   per_word packed indices when per_word > 0)
  *   -- later failures are CORRUPT with the output zero-filled --
  *   label width = the volume's, coder in {RAW4, RANS}, RAW4 has log2W 0,
  *   RANS has log2W <= 8; header and palette fit the record; sym_end is
@@ -598,7 +599,7 @@ typedef struct {
  *   volume's frequency table sums to 4096.
  */
 static int parse_record(const uint8_t* c, uint64_t bytes, uint32_t id, int lod, uint64_t out_off, uint64_t out_cap,
-                        rec_view* r, int* write_ok) {
+                        uint32_t per_word, rec_view* r, int* write_ok) {
     *write_ok = 0;
     uint32_t n_bricks = rd32(c + 32);
     uint64_t off_pos = rd64(c + 80);
@@ -612,6 +613,7 @@ static int parse_record(const uint8_t* c, uint64_t bytes, uint32_t id, int lod, 
     if (r->L < 1 || r->L > 6) return ST_CORRUPT;
     if (lod < 0 || lod > r->L) return ST_INVALID;
     uint64_t S = (uint64_t)1 << (r->L - lod), n_out = S * S * S;
+    if (per_word) n_out = (n_out + per_word - 1) / per_word; /* packed indices: 32-bit words */
     if (out_off > out_cap || n_out > out_cap - out_off) return ST_INVALID;
     *write_ok = 1;
     if (r->lb != (int)rd32(c + 24) || r->coder > 1 || (r->coder == CODER_RAW4 && r->log2W != 0) ||
@@ -666,32 +668,52 @@ static int read_symbols(const uint8_t* c, const rec_view* r, uint32_t n, uint8_t
 }
 
 /*
- * Decode brick `id` at LOD `lod` into out (S^3 labels, x fastest, S = b>>lod).
- * Level t = L - lod is reconstructed; levels 0..t are read in order and
- * nodes within a level in Morton order.  A node whose parent is implied or
- * stopped is implied and takes its parent's label; any other node consumes
- * one symbol s: op = s & 7, stop = s >> 3 (the stop bit of level t is not
- * needed).  PARENT copies the parent; NX/NY/NZ copy the node at x-1 / y-1 /
- * z-1 of the same level; ADV takes palette[n] and n += 1; LAST takes
- * palette[n-1]; DELTA reads its entry chain into delta and takes
- * palette[n-delta], where n counts the ADV operations so far.
+ * Cache-paletted output (Methods > Memory management > Cache paletting): n
+ * palette indices of `bits` bits each (1..31) packed floor(32 / bits) to a
+ * 32-bit word, index k in word k / e at bit (k % e) * bits (e = entries per
+ * word), the unused high bits of every word zero.  Writes ceil(n / e) words.
+ */
+void oracle_pack_indices(const uint32_t* idx, uint64_t n, int bits, uint32_t* out) {
+    uint64_t e = (uint64_t)(32 / bits), words = (n + e - 1) / e;
+    for (uint64_t w = 0; w < words; w++) out[w] = 0;
+    for (uint64_t k = 0; k < n; k++) out[k / e] |= idx[k] << ((k % e) * (uint64_t)bits);
+}
+
+/*
+ * Decode brick `id` at LOD `lod` into out at element offset out_off:
+ * S^3 labels (x fastest, S = b>>lod) when bits = 0, else the S^3 palette
+ * indices packed by oracle_pack_indices into 32-bit words at word offset
+ * out_off.  Level t = L - lod is reconstructed; levels 0..t are read in
+ * order and nodes within a level in Morton order.  A node whose parent is
+ * implied or stopped is implied and takes its parent's palette index; any
+ * other node consumes one symbol s: op = s & 7, stop = s >> 3 (the stop bit
+ * of level t is not needed).  PARENT copies the parent; NX/NY/NZ copy the
+ * node at x-1 / y-1 / z-1 of the same level; ADV takes index n and n += 1;
+ * LAST takes n-1; DELTA reads its entry chain into delta and takes n-delta,
+ * where n counts the ADV operations so far.  A voxel's label is the palette
+ * entry at its index.
  * CORRUPT verdicts: PARENT at level 0, a neighbour outside the brick,
  * ADV with n >= palette_count, LAST with n = 0, delta = 0 or > n, op 7,
  * a level whose symbols do not end exactly at sym_end[level] (including a
  * delta chain running past it), RANS words exhausted, and at t = L an ADV
- * count different from palette_count.
+ * count different from palette_count.  With bits > 0 a task that passes the
+ * record checks is INVALID (output untouched) when t = 6 or the record's
+ * palette has more than 2^bits entries.
  */
 static int decode_one(const uint8_t* c, uint64_t bytes, uint32_t id, int lod, uint64_t out_off, uint64_t out_cap, void* out,
-                      int lb_vol) {
+                      int lb_vol, int bits) {
     rec_view r;
     int write_ok;
     memset(&r, 0, sizeof(r));
-    int st = parse_record(c, bytes, id, lod, out_off, out_cap, &r, &write_ok);
+    uint32_t per_word = bits ? (uint32_t)(32 / bits) : 0;
+    int st = parse_record(c, bytes, id, lod, out_off, out_cap, per_word, &r, &write_ok);
     int L = r.L, t = L - lod;
     uint64_t S = write_ok ? (uint64_t)1 << t : 0, n_out = S * S * S;
+    uint64_t n_units = per_word ? (n_out + per_word - 1) / per_word : n_out;
     uint64_t* G[7] = {0};
     uint8_t* expand[7] = {0};
     uint8_t* sym = NULL;
+    if (st == ST_OK && bits && (t == 6 || (uint64_t)r.pc > ((uint64_t)1 << bits))) return ST_INVALID;
     if (st != ST_OK) goto done;
     {
         uint32_t nsym = r.sym_end[t];
@@ -728,11 +750,11 @@ static int decode_one(const uint8_t* c, uint64_t bytes, uint32_t id, int lod, ui
                     break;
                 case OP_ADV:
                     if (n >= r.pc) st = ST_CORRUPT;
-                    else v = get_label(r.pal, r.lb, n++);
+                    else v = n++;
                     break;
                 case OP_LAST:
                     if (n == 0) st = ST_CORRUPT;
-                    else v = get_label(r.pal, r.lb, n - 1);
+                    else v = n - 1;
                     break;
                 case OP_DELTA: {
                     uint64_t delta = 0;
@@ -743,7 +765,7 @@ static int decode_one(const uint8_t* c, uint64_t bytes, uint32_t id, int lod, ui
                         delta = delta_step(delta, e);
                     } while (e & 8);
                     if (st == ST_OK && (delta == 0 || delta > n)) st = ST_CORRUPT;
-                    if (st == ST_OK) v = get_label(r.pal, r.lb, n - (uint32_t)delta);
+                    if (st == ST_OK) v = n - (uint32_t)delta;
                     break;
                 }
                 default:
@@ -755,17 +777,29 @@ static int decode_one(const uint8_t* c, uint64_t bytes, uint32_t id, int lod, ui
             if (st == ST_OK && pos != r.sym_end[i]) st = ST_CORRUPT;
         }
         if (st == ST_OK && t == L && n != r.pc) st = ST_CORRUPT;
-        if (st == ST_OK) {
+        if (st == ST_OK && !bits) {
             for (uint64_t zz = 0; zz < S; zz++)
                 for (uint64_t yy = 0; yy < S; yy++)
                     for (uint64_t xx = 0; xx < S; xx++)
                         put_label(out, lb_vol, out_off + (zz * S + yy) * S + xx,
-                                  G[t][morton((uint32_t)xx, (uint32_t)yy, (uint32_t)zz, t)]);
+                                  get_label(r.pal, r.lb, G[t][morton((uint32_t)xx, (uint32_t)yy, (uint32_t)zz, t)]));
+        } else if (st == ST_OK) {
+            uint32_t* idx = (uint32_t*)malloc(sizeof(uint32_t) * n_out);
+            for (uint64_t zz = 0; zz < S; zz++)
+                for (uint64_t yy = 0; yy < S; yy++)
+                    for (uint64_t xx = 0; xx < S; xx++)
+                        idx[(zz * S + yy) * S + xx] =
+                            (uint32_t)G[t][morton((uint32_t)xx, (uint32_t)yy, (uint32_t)zz, t)];
+            oracle_pack_indices(idx, n_out, bits, (uint32_t*)out + out_off);
+            free(idx);
         }
     }
 done:
     if (st == ST_CORRUPT && write_ok)
-        for (uint64_t k = 0; k < n_out; k++) put_label(out, lb_vol, out_off + k, 0);
+        for (uint64_t k = 0; k < n_units; k++) {
+            if (bits) ((uint32_t*)out)[out_off + k] = 0;
+            else put_label(out, lb_vol, out_off + k, 0);
+        }
     for (int i = 0; i < 7; i++) { free(G[i]); free(expand[i]); }
     free(sym);
     return st;
@@ -778,9 +812,9 @@ done:
  * record: output zero-filled when its range is valid).  Returns 0, or -1
  * when the container header itself is unusable.
  */
-int oracle_decode_tasks(const uint8_t* c, uint64_t bytes, const uint32_t* ids, const uint8_t* lods,
-                        const uint64_t* out_offsets, uint32_t n, void* out, uint64_t out_cap, uint32_t* status,
-                        int nthreads) {
+static int decode_list(const uint8_t* c, uint64_t bytes, const uint32_t* ids, const uint8_t* lods,
+                       const uint64_t* out_offsets, uint32_t n, void* out, uint64_t out_cap, uint32_t* status,
+                       int bits, int nthreads) {
     if (bytes < OR_HDR_BYTES || rd32(c) != OR_MAGIC || rd32(c + 4) != OR_VERSION) return -1;
     int lb = (int)rd32(c + 24);
     if (lb != 4 && lb != 8) return -1;
@@ -789,11 +823,43 @@ int oracle_decode_tasks(const uint8_t* c, uint64_t bytes, const uint32_t* ids, c
     (void)nthreads;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1)
     for (long j = 0; j < (long)n; j++)
-        status[j] = (uint32_t)decode_one(c, bytes, ids[j], lods[j], out_offsets[j], out_cap, out, lb);
+        status[j] = (uint32_t)decode_one(c, bytes, ids[j], lods[j], out_offsets[j], out_cap, out, lb, bits);
     return 0;
 }
 
+int oracle_decode_tasks(const uint8_t* c, uint64_t bytes, const uint32_t* ids, const uint8_t* lods,
+                        const uint64_t* out_offsets, uint32_t n, void* out, uint64_t out_cap, uint32_t* status,
+                        int nthreads) {
+    return decode_list(c, bytes, ids, lods, out_offsets, n, out, out_cap, status, 0, nthreads);
+}
+
+/*
+ * The same task list decoded to cache-paletted form: out is 32-bit words,
+ * out_offsets and out_cap count words, task j writes its packed indices
+ * (oracle_pack_indices with `bits`, 1..31) at word out_offsets[j].
+ * Returns 0, or -1 for an unusable header or bits outside 1..31.
+ */
+int oracle_decode_tasks_paletted(const uint8_t* c, uint64_t bytes, const uint32_t* ids, const uint8_t* lods,
+                                 const uint64_t* out_offsets, uint32_t n, uint32_t* out, uint64_t out_cap,
+                                 uint32_t* status, int bits, int nthreads) {
+    if (bits < 1 || bits > 31) return -1;
+    return decode_list(c, bytes, ids, lods, out_offsets, n, out, out_cap, status, bits, nthreads);
+}
+
 /* ------------------------------------------------------------ inspection */
+/*
+ * Palette of one record (for tests): copies up to cap entries of the
+ * volume's label width into out; returns the palette count, or -1.
+ */
+int64_t oracle_record_palette(const uint8_t* c, uint64_t bytes, uint32_t id, uint64_t* out, uint32_t cap) {
+    rec_view r;
+    int write_ok;
+    memset(&r, 0, sizeof(r));
+    if (bytes < OR_HDR_BYTES || parse_record(c, bytes, id, 0, 0, UINT64_MAX, 0, &r, &write_ok) != ST_OK) return -1;
+    for (uint32_t k = 0; k < r.pc && k < cap; k++) out[k] = get_label(r.pal, r.lb, k);
+    return (int64_t)r.pc;
+}
+
 /*
  * Symbol stream and palette of one record (for tests).  Fills sym (cap
  * entries), sym_end (7), and returns the symbol count (sym_end[L]), or -1.
@@ -803,7 +869,7 @@ int64_t oracle_record_symbols(const uint8_t* c, uint64_t bytes, uint32_t id, uin
     rec_view r;
     int write_ok;
     memset(&r, 0, sizeof(r));
-    if (parse_record(c, bytes, id, 0, 0, UINT64_MAX, &r, &write_ok) != ST_OK) return -1;
+    if (parse_record(c, bytes, id, 0, 0, UINT64_MAX, 0, &r, &write_ok) != ST_OK) return -1;
     if (r.sym_end[r.L] > cap) return -1;
     if (read_symbols(c, &r, r.sym_end[r.L], sym) != 0) return -1;
     for (int i = 0; i <= r.L; i++) sym_end[i] = r.sym_end[i];

@@ -422,3 +422,109 @@ def test_workload_generators_shape():
     assert np.array_equal(a, b)  # slab-wise generation is exact
     kinds = [synth.uneven_brick_u64(32, 0, i)[1] for i in range(200)]
     assert 0.25 < kinds.count(0) / 200 < 0.55 and kinds.count(2) > 10
+
+
+# ------------------------------------------------- cache-paletted output
+def _unpack(words, n, bits):
+    """Plain unpacking of the cache-paletted form, written out here."""
+    e = 32 // bits
+    return np.array([(int(words[k // e]) >> ((k % e) * bits)) & ((1 << bits) - 1) for k in range(n)], dtype=np.uint32)
+
+
+def test_palette_packing_golden():
+    # Methods > Memory management > Cache paletting: floor(32/I) entries per word
+    for line in _lines("palette_pack.txt"):
+        b, idx, words = (x.strip() for x in line.split("|"))
+        got = oracle.pack_indices([int(v) for v in idx.split()], int(b))
+        assert [int(w, 16) for w in words.split()] == got.tolist()
+
+
+def test_palette_packing_roundtrip_every_width():
+    rng = np.random.default_rng(0)
+    for bits in range(1, 32):
+        idx = rng.integers(0, 1 << bits, size=int(rng.integers(1, 300)), dtype=np.uint64).astype(np.uint32)
+        words = oracle.pack_indices(idx, bits)
+        e = 32 // bits
+        assert len(words) == -(-len(idx) // e)
+        assert np.array_equal(_unpack(words, len(idx), bits), idx)
+        # bits above the last entry of every word stay zero
+        if e * bits < 32:
+            assert (words >> np.uint32(e * bits) == 0).all()
+
+
+@pytest.mark.parametrize("lb", [4, 8])
+def test_paletted_decode_is_the_first_occurrence_index(lb):
+    # With unlimited back references (DELTA on) a palette holds each label once,
+    # so a voxel's index is the position of its label in its brick's palette;
+    # unpacked through the palette the paletted decode is the label decode.
+    if lb == 4:
+        c = oracle.encode_volume(synth.voronoi_voids(64, 60, seed=5), 5)
+    else:
+        bricks = [synth.test_brick_u64(32, k % 3, 2 + 9 * k, base=1, seed=k).reshape(-1) for k in range(4)]
+        c = oracle.encode_bricks(np.concatenate(bricks), [5] * 4, 8)
+    n = oracle.header(c)["n_bricks"]
+    pmax = max(len(oracle.record_palette(c, k)) for k in range(n))
+    bits = max(1, int(np.ceil(np.log2(pmax))))
+    for lod in (0, 1, 2, 5):
+        ids = np.arange(n)
+        lods = np.full(n, lod)
+        S3 = (32 >> lod) ** 3
+        offs, tot = oracle.dense_offsets([5] * n, lods)
+        labels, st = oracle.decode_tasks(c, ids, lods, offs, tot, lb, nthreads=4)
+        assert (st == 0).all()
+        wcount = oracle.paletted_words(np.full(n, S3), bits)
+        woffs = np.concatenate([[0], np.cumsum(wcount)[:-1]]).astype(np.uint64)
+        words, pst = oracle.decode_tasks_paletted(c, ids, lods, woffs, int(wcount.sum()), bits, nthreads=4)
+        assert (pst == 0).all()
+        for k in range(n):
+            pal = oracle.record_palette(c, k)
+            a = int(woffs[k])
+            idx = _unpack(words[a:a + int(wcount[k])], S3, bits)
+            lab = labels[offs[k]:offs[k] + S3].astype(np.uint64)
+            assert np.array_equal(pal[idx], lab)
+            first = {int(v): i for i, v in reversed(list(enumerate(pal.tolist())))}
+            assert np.array_equal(idx, np.array([first[int(v)] for v in lab], dtype=np.uint32))
+
+
+def test_paletted_duplicates_keep_the_stream_index():
+    # without back references a palette repeats labels; the index is the one the
+    # operation stream designates, and it still maps to the decoded label
+    brick = synth.test_brick_u64(16, 1, 6, base=1, seed=3).astype(np.uint32)
+    c = oracle.encode_bricks(brick.reshape(-1), [4], 4, op_mask=0)
+    pal = oracle.record_palette(c, 0)
+    assert len(pal) > len(set(pal.tolist()))
+    bits = int(np.ceil(np.log2(len(pal))))
+    words, st = oracle.decode_tasks_paletted(c, [0], [0], [0], int(oracle.paletted_words(4096, bits)), bits)
+    assert st[0] == 0
+    idx = _unpack(words, 4096, bits)
+    assert np.array_equal(pal[idx], brick.reshape(-1).astype(np.uint64))
+    # ... and is not simply the label's first palette position
+    first = {int(v): i for i, v in reversed(list(enumerate(pal.tolist())))}
+    assert any(first[int(pal[i])] != i for i in set(idx.tolist()))
+
+
+def test_paletted_invalid_and_corrupt_tasks():
+    c = oracle.encode_volume(synth.voronoi_voids(64, 60, seed=5), 5)
+    pmax = max(len(oracle.record_palette(c, k)) for k in range(8))
+    small = max(1, int(np.ceil(np.log2(pmax))) - 1)  # too few bits for the largest palette
+    ids = np.arange(8)
+    wcount = oracle.paletted_words(np.full(8, 32768), small)
+    woffs = np.concatenate([[0], np.cumsum(wcount)[:-1]]).astype(np.uint64)
+    words, st = oracle.decode_tasks_paletted(c, ids, np.zeros(8), woffs, int(wcount.sum()), small)
+    pcs = np.array([len(oracle.record_palette(c, k)) for k in range(8)])
+    assert np.array_equal(st == 1, pcs > (1 << small))
+    for k in np.nonzero(st == 1)[0]:  # untouched
+        a = int(woffs[k])
+        assert (words[a:a + int(wcount[k])] == 0xA5A5A5A5).all()
+    # 64^3 bricks at full resolution have no paletted form
+    b, _ = synth.uneven_brick_u64(64, 3, 1)
+    c64 = oracle.encode_bricks(b.reshape(-1), [6], 8)
+    _, st = oracle.decode_tasks_paletted(c64, [0, 0], [0, 1], [0, 100000], 200000, 18)
+    assert list(st) == [1, 0]
+    # a damaged record zero-fills its words
+    offs = oracle.brick_offsets(c)
+    bad = bytearray(c)
+    bad[int(offs[2]) + 8] = 0xFF  # sym_end[0] of brick 2: no longer ordered
+    nw = int(oracle.paletted_words(32768, small + 1))
+    words, st = oracle.decode_tasks_paletted(bytes(bad), [2], [0], [0], nw, small + 1)
+    assert st[0] == 2 and (words[:nw] == 0).all()
