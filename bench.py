@@ -278,6 +278,73 @@ def measure(wl: Workload, args, dev):
     return res
 
 
+def measure_paletted(wl: Workload, args, dev, shape):
+    """The same task list decoded to cache-paletted form (packed palette
+    indices, I = ceil(log2 |P|max) bits, floor(32/I) per 32-bit word) with the
+    plan shape the label run chose; bit-exact against the oracle's paletted
+    decode of every task."""
+    import torch
+    import oracle
+    import paper_2609_36898_amd as P
+    dv = P.DeviceVolume(wl.container, device=dev)
+    n = len(wl.ids)
+    bits = P.csgv.palette_bits_for(dv.info.max_palette)
+    log2b = P.brick_log2b(wl.container, dv.info)[wl.ids.astype(np.int64)]
+    voxels = np.int64(1) << (3 * (log2b - wl.lods.astype(np.int64)))
+    words = P.csgv.paletted_words(voxels, bits)
+    offs = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.uint64)
+    total = int(words.sum())
+    d_ids = torch.from_numpy(wl.ids.view(np.int32)).to(dev)
+    d_lods = torch.from_numpy(wl.lods).to(dev)
+    d_offs = torch.from_numpy(offs.view(np.int64)).to(dev)
+    out = torch.empty(total, dtype=torch.int32, device=dev)
+    status = torch.full((n,), -1, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    plan = P.csgv_plan(dv.info, n, wg_size=shape["wg_size"], lds_slots=shape["lds_slots"], palette_bits=bits)
+
+    def step():
+        plan.launch(stream, dv.tensor, d_ids, d_lods, d_offs, n, out, total, status)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    plan.set_timing(True)
+    kms = []
+    for _ in range(max(3, args.steps)):
+        step()
+        kms.append(plan.last_kernel_ms())
+    plan.destroy()
+    torch.cuda.synchronize()
+    kernel_ms = float(np.mean(kms))
+    recs = np.frombuffer(wl.container, dtype=np.uint64, count=dv.info.n_bricks + 1, offset=int(dv.info.offsets_pos))
+    rec_bytes = float((recs[wl.ids.astype(np.int64) + 1] - recs[wl.ids.astype(np.int64)]).sum())
+    alg = rec_bytes + 4.0 * total
+    got = out.cpu().numpy().view(np.uint32)
+    st = status.cpu().numpy()
+    want, wst = oracle.decode_tasks_paletted(wl.container, wl.ids, wl.lods, offs, total, bits, nthreads=cpu_threads())
+    exact = bool((st == 0).all()) and bool((wst == 0).all()) and bool(np.array_equal(got, want))
+    vox = float(voxels.sum())
+    del out, dv
+    torch.cuda.empty_cache()
+    kgbs = alg / (kernel_ms * 1e-3) / 1e9
+    return {"value": round(vox / (ms * 1e-3) / 1e9, 3) if exact else None, "unit": "GVoxel/s",
+            "ms_per_step": round(ms, 4), "bit_exact": exact,
+            "config": {"workload": wl.config["workload"] + "_paletted", "palette_bits": bits,
+                       "max_palette": int(P.csgv_volume_parse(wl.container).max_palette),
+                       "indices_per_word": 32 // bits, "words_per_launch": total,
+                       "label_bytes_saved": round(1.0 - 4.0 * total / (vox * wl.label_bytes), 4)},
+            "roofline": {"bound": "hbm", "achieved": round(kgbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(kgbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": DECODE_KERNEL,
+                         "kernel_ms": round(kernel_ms, 4), "alg_bytes_per_launch": alg}}
+
+
 def measure_served(wl: Workload, args, dev):
     """The served workload: the compressed volume and a 24 GiB decoded-brick
     cache resident in HBM, a stream of frustum requests through the server.
@@ -550,6 +617,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain one-launch-per-brick legs")
     ap.add_argument("--no-tune", action="store_true", help="default launch shape instead of the autotuner")
+    ap.add_argument("--no-paletted", action="store_true", help="skip the cache-paletted leg of neurite1024")
     ap.add_argument("--tune-cache", default=os.environ.get("CSGV_TUNE_CACHE", "/tmp/csgv_autotune.txt"))
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run device-to-device copies of CALIB_COPY_BYTES (reference kernel for HBM counter scaling)")
@@ -581,6 +649,10 @@ def main():
     for name in names:
         wl = build_workload(name)
         r = measure_served(wl, args, dev) if wl.served else measure(wl, args, dev)
+        if name == "neurite1024" and not args.no_paletted:
+            r["paletted"] = measure_paletted(wl, args, dev, r["shape"])
+            _log("%s paletted: %.2f GVoxel/s, bit_exact %s" % (name, r["paletted"]["value"] or 0.0,
+                                                                r["paletted"]["bit_exact"]))
         _log("%s: %.2f GVoxel/s, roofline %.3f, bit_exact %s" % (
             name, r["value"], r["roofline"]["frac"], r["bit_exact"]))
         if "served" in r:

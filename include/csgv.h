@@ -100,6 +100,7 @@ typedef struct {
     uint64_t total_bytes;  /* container size */
     uint32_t neighbor_mode;
     uint32_t max_log2b;    /* largest log2(brick side) any record claims (sizes decoder scratch) */
+    uint32_t max_palette;  /* largest palette count of any record (|P|max of cache paletting) */
 } csgv_volume_info;
 
 /* Launch shape.  Zero (or -1 for sort_tasks) selects the default. */
@@ -114,7 +115,24 @@ typedef struct {
     int lds_slots;       /* LDS split: 16-bit slots per work-group for the explicit nodes of
                             level 5 (bricks needing more use global scratch); the area also
                             holds the rANS table, so 8192..32760; default 10240             */
+    int palette_bits;    /* 0: labels (default).  I in 1..31: cache-paletted output, see
+                            CSGV_PALETTED_WORDS                                             */
 } csgv_decode_opts;
+
+/*
+ * Cache-paletted output (Methods > Memory management > Cache paletting):
+ * with palette_bits = I a task writes, instead of its S^3 labels, their
+ * indices into the brick's palette (the index the operation stream assigns:
+ * the label's position in the palette), I bits each, floor(32 / I) per 32-bit
+ * word: voxel k of the cube (x fastest) sits in word k / e at bit
+ * (k mod e) * I, e = floor(32 / I), unused high bits zero.  d_out is then
+ * 32-bit words and d_out_offsets / out_capacity count words; a task occupies
+ * CSGV_PALETTED_WORDS(S^3, I) words.  I = max(1, ceil(log2(max_palette)))
+ * fits every brick of a volume.  A task whose record has more than 2^I
+ * palette entries, or that asks for a 64^3 cube, is CSGV_TASK_INVALID
+ * (output untouched).
+ */
+#define CSGV_PALETTED_WORDS(voxels, bits) (((voxels) + 32u / (bits) - 1u) / (32u / (bits)))
 
 /*
  * Parse and validate a container held in host memory (the "Brick Starts"

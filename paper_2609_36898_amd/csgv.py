@@ -41,12 +41,14 @@ class VolumeInfo(ctypes.Structure):
         ("total_bytes", ctypes.c_uint64),
         ("neighbor_mode", ctypes.c_uint32),
         ("max_log2b", ctypes.c_uint32),
+        ("max_palette", ctypes.c_uint32),
     ]
 
 
 class DecodeOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("wg_size", ctypes.c_int), ("wgs_per_cu", ctypes.c_int),
-                ("sort_tasks", ctypes.c_int), ("bricks_per_wave", ctypes.c_int), ("lds_slots", ctypes.c_int)]
+                ("sort_tasks", ctypes.c_int), ("bricks_per_wave", ctypes.c_int), ("lds_slots", ctypes.c_int),
+                ("palette_bits", ctypes.c_int)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -135,16 +137,17 @@ def csgv_volume_parse(container) -> VolumeInfo:
     return info
 
 
-def _opts(mode=None, wg_size=0, wgs_per_cu=0, sort_tasks=-1, bricks_per_wave=0, lds_slots=0):
-    if mode is None:
+def _opts(mode=None, wg_size=0, wgs_per_cu=0, sort_tasks=-1, bricks_per_wave=0, lds_slots=0, palette_bits=0):
+    if mode is None and not palette_bits:
         return None
-    return DecodeOpts(mode, wg_size, wgs_per_cu, sort_tasks, bricks_per_wave, lds_slots)
+    return DecodeOpts(MODE_PLAIN if mode is None else mode, wg_size, wgs_per_cu, sort_tasks, bricks_per_wave,
+                      lds_slots, palette_bits)
 
 
 def csgv_decode_bricks(stream, vol: VolumeInfo, d_container, d_brick_ids, d_lods, d_out_offsets, n: int, d_out,
                        out_capacity: int, d_status=None, mode=None, wg_size=0, wgs_per_cu=0, sort_tasks=-1,
-                       bricks_per_wave=0, lds_slots=0):
-    o = _opts(mode, wg_size, wgs_per_cu, sort_tasks, bricks_per_wave, lds_slots)
+                       bricks_per_wave=0, lds_slots=0, palette_bits=0):
+    o = _opts(mode, wg_size, wgs_per_cu, sort_tasks, bricks_per_wave, lds_slots, palette_bits)
     rc = _lib.csgv_decode_bricks(_stream(stream), ctypes.byref(vol), _ptr(d_container), _ptr(d_brick_ids),
                                  _ptr(d_lods), _ptr(d_out_offsets), n, _ptr(d_out), out_capacity, _ptr(d_status),
                                  None if o is None else ctypes.byref(o))
@@ -153,13 +156,24 @@ def csgv_decode_bricks(stream, vol: VolumeInfo, d_container, d_brick_ids, d_lods
 
 def csgv_decode_bricks_noalloc(stream, vol: VolumeInfo, d_container, d_brick_ids, d_lods, d_out_offsets, n: int,
                                d_out, out_capacity: int, d_status=None, mode=None, wg_size=0, wgs_per_cu=0,
-                               sort_tasks=-1, bricks_per_wave=0, lds_slots=0):
+                               sort_tasks=-1, bricks_per_wave=0, lds_slots=0, palette_bits=0):
     """csgv_decode_bricks on the library's fixed scratch (no allocation; calls on one GPU must not overlap)."""
-    o = _opts(mode, wg_size, wgs_per_cu, sort_tasks, bricks_per_wave, lds_slots)
+    o = _opts(mode, wg_size, wgs_per_cu, sort_tasks, bricks_per_wave, lds_slots, palette_bits)
     rc = _lib.csgv_decode_bricks_noalloc(_stream(stream), ctypes.byref(vol), _ptr(d_container), _ptr(d_brick_ids),
                                          _ptr(d_lods), _ptr(d_out_offsets), n, _ptr(d_out), out_capacity,
                                          _ptr(d_status), None if o is None else ctypes.byref(o))
     _check(rc, "csgv_decode_bricks_noalloc")
+
+
+def palette_bits_for(max_palette: int) -> int:
+    """Index width that fits every brick of a volume: max(1, ceil(log2(max_palette)))."""
+    return max(1, int(max(int(max_palette), 1) - 1).bit_length())
+
+
+def paletted_words(voxels, bits: int):
+    """32-bit words of a cube of `voxels` packed palette indices (CSGV_PALETTED_WORDS)."""
+    e = 32 // bits
+    return (np.asarray(voxels, dtype=np.int64) + e - 1) // e
 
 
 def csgv_check_status(d_status, n: int, stream=None) -> bool:
@@ -174,10 +188,10 @@ class csgv_plan:
     """Owner of a csgv_plan* (csgv_plan_create / csgv_plan_destroy)."""
 
     def __init__(self, vol: VolumeInfo, max_tasks: int, wg_size: int = 0, wgs_per_cu: int = 0, sort_tasks: int = -1,
-                 bricks_per_wave: int = 0, lds_slots: int = 0):
+                 bricks_per_wave: int = 0, lds_slots: int = 0, palette_bits: int = 0):
         self._vol = vol
         self._h = ctypes.c_void_p()
-        o = DecodeOpts(MODE_PERSISTENT, wg_size, wgs_per_cu, sort_tasks, bricks_per_wave, lds_slots)
+        o = DecodeOpts(MODE_PERSISTENT, wg_size, wgs_per_cu, sort_tasks, bricks_per_wave, lds_slots, palette_bits)
         _check(_lib.csgv_plan_create(ctypes.byref(vol), max_tasks, ctypes.byref(o), ctypes.byref(self._h)),
                "csgv_plan_create")
 
@@ -193,8 +207,8 @@ class csgv_plan:
         _check(_lib.csgv_plan_set_timing(self._h, int(enable)), "csgv_plan_set_timing")
 
     def set_opts(self, wg_size: int = 0, wgs_per_cu: int = -1, sort_tasks: int = -1, bricks_per_wave: int = 0,
-                 lds_slots: int = 0):
-        o = DecodeOpts(MODE_PERSISTENT, wg_size, wgs_per_cu, sort_tasks, bricks_per_wave, lds_slots)
+                 lds_slots: int = 0, palette_bits: int = -1):
+        o = DecodeOpts(MODE_PERSISTENT, wg_size, wgs_per_cu, sort_tasks, bricks_per_wave, lds_slots, palette_bits)
         _check(_lib.csgv_plan_set_opts(self._h, ctypes.byref(o)), "csgv_plan_set_opts")
 
     def get_opts(self) -> DecodeOpts:
@@ -357,7 +371,7 @@ class csgv_server:
         self._h = ctypes.c_void_p()
         self._l2 = None if brick_log2b is None else np.ascontiguousarray(np.asarray(brick_log2b, dtype=np.uint8))
         cfg = ServerConfig(n_streams, max_batch, int(keep_pinned),
-                           DecodeOpts(MODE_PERSISTENT, wg_size, 0, sort_tasks, 0, lds_slots))
+                           DecodeOpts(MODE_PERSISTENT, wg_size, 0, sort_tasks, 0, lds_slots, 0))
         _scheck(_lib.csgv_server_create(ctypes.byref(vol), _ptr(d_container),
                                         None if self._l2 is None else self._l2.ctypes.data, _ptr(d_cache),
                                         cache_elements, ctypes.byref(cfg), ctypes.byref(self._h)),

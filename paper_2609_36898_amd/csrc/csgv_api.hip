@@ -134,6 +134,7 @@ csgv_status check_opts(const csgv_decode_opts* o) {
                     kMinCap16);
     if (o->bricks_per_wave < 0) return fail(CSGV_EINVAL, "bricks_per_wave %d", o->bricks_per_wave);
     if (o->wgs_per_cu < -1) return fail(CSGV_EINVAL, "wgs_per_cu %d", o->wgs_per_cu);
+    if (o->palette_bits < -1 || o->palette_bits > 31) return fail(CSGV_EINVAL, "palette_bits %d (0..31)", o->palette_bits);
     return CSGV_OK;
 }
 
@@ -228,14 +229,17 @@ csgv_status csgv_volume_parse(const void* h_container, uint64_t bytes, csgv_volu
         8ull * ((uint64_t)v.n_bricks + 1) > v.total_bytes - v.offsets_pos)
         return fail(CSGV_EINVAL, "offset table outside the container");
     // largest brick side any record claims (sizes the decoder's scratch)
-    uint32_t mx = 0;
+    // and the largest palette (|P|max of cache paletting)
+    uint32_t mx = 0, mp = 0;
     for (uint64_t k = 0; k < v.n_bricks; ++k) {
         const uint64_t a = rd64(h + v.offsets_pos + 8 * k), b = rd64(h + v.offsets_pos + 8 * k + 8);
         if (a > b || b > v.total_bytes || b - a < 8) continue;
         const uint32_t L = h[a + 1];
         if (L >= 1 && L <= kMaxLog2b) mx = std::max(mx, L);
+        mp = std::max(mp, rd32(h + a + 4));
     }
     v.max_log2b = mx ? mx : 1;
+    v.max_palette = mp;
     *out = v;
     return CSGV_OK;
 }
@@ -284,6 +288,7 @@ csgv_status prepare_call(const csgv_volume_info* vol, const void* d_container, c
     if (*mode != CSGV_MODE_PLAIN && *mode != CSGV_MODE_PERSISTENT) return fail(CSGV_EINVAL, "unknown mode %d", *mode);
     *P = make_params(vol, d_container, d_brick_ids, d_lods, d_out_offsets, n, d_out, out_capacity, d_status);
     if (opts && opts->lds_slots > 0) P->cap16 = std::max<uint32_t>((uint32_t)opts->lds_slots, kMinCap16) & ~7u;
+    if (opts && opts->palette_bits > 0) P->pal_bits = (uint32_t)opts->palette_bits;
     *wg = opts && opts->wg_size ? opts->wg_size : 256;
     *per_cu = opts && opts->wgs_per_cu > 0 ? opts->wgs_per_cu : resident_per_cu(*wg, P->cap16);
     return CSGV_OK;
@@ -354,7 +359,7 @@ struct csgv_plan {
         void* out;
         uint64_t cap;
         void* status;
-        int wg, grid, sort, cap16;
+        int wg, grid, sort, cap16, pal_bits;
         bool operator==(const Key& o) const { return memcmp(this, &o, sizeof(Key)) == 0; }
     } key;
     bool have_key = false;
@@ -369,6 +374,7 @@ uint32_t plan_grid(const csgv_plan* p, uint32_t n) {
 csgv_status plan_enqueue(csgv_plan* p, hipStream_t s, const Params& P0, bool with_events) {
     Params P = P0;
     P.cap16 = std::max<uint32_t>((uint32_t)p->opts.lds_slots, kMinCap16) & ~7u;
+    P.pal_bits = p->opts.palette_bits > 0 ? (uint32_t)p->opts.palette_bits : 0u;
     hipError_t e = enqueue_persistent(P, p->b, &p->vol, p->opts.wg_size, plan_grid(p, P.n_tasks),
                                       p->opts.sort_tasks != 0, s, with_events ? p->ev0 : nullptr,
                                       with_events ? p->ev1 : nullptr);
@@ -428,6 +434,7 @@ csgv_status csgv_plan_create(const csgv_volume_info* vol, uint32_t max_tasks, co
     p->opts.sort_tasks = opts && opts->sort_tasks >= 0 ? opts->sort_tasks : 1;
     p->opts.bricks_per_wave = opts && opts->bricks_per_wave > 0 ? opts->bricks_per_wave : 1;
     p->opts.lds_slots = opts && opts->lds_slots > 0 ? opts->lds_slots : (int)kDefaultCap16;
+    p->opts.palette_bits = opts && opts->palette_bits > 0 ? opts->palette_bits : 0;
     if ((st = plan_alloc(p)) != CSGV_OK) {
         delete p;
         return st;
@@ -463,6 +470,7 @@ csgv_status csgv_plan_set_opts(csgv_plan* p, const csgv_decode_opts* o) {
     if (o->sort_tasks >= 0) n.sort_tasks = o->sort_tasks ? 1 : 0;
     if (o->bricks_per_wave > 0) n.bricks_per_wave = o->bricks_per_wave;
     if (o->lds_slots > 0) n.lds_slots = o->lds_slots;
+    if (o->palette_bits >= 0) n.palette_bits = o->palette_bits;
     const csgv_decode_opts old = p->opts;
     p->opts = n;
     if ((st = plan_alloc(p)) != CSGV_OK) {
@@ -491,7 +499,7 @@ csgv_status csgv_plan_launch(csgv_plan* p, hipStream_t stream, const void* d_con
     memset(&k, 0, sizeof(k));
     k.c = d_container; k.ids = d_brick_ids; k.lods = d_lods; k.offs = d_out_offsets; k.n = n; k.out = d_out;
     k.cap = out_capacity; k.status = d_status; k.wg = p->opts.wg_size; k.grid = (int)p->grid;
-    k.sort = p->opts.sort_tasks; k.cap16 = p->opts.lds_slots;
+    k.sort = p->opts.sort_tasks; k.cap16 = p->opts.lds_slots; k.pal_bits = p->opts.palette_bits;
     if (!p->have_key || !(k == p->key) || !p->exec) {
         if (p->exec) {
             (void)hipGraphExecDestroy(p->exec);
@@ -561,10 +569,10 @@ std::string tune_key(const csgv_plan* p, const std::vector<uint8_t>& lods, uint3
     uint32_t hist[8] = {0};
     for (uint8_t l : lods) ++hist[l < 7 ? l : 7];
     char buf[512];
-    snprintf(buf, sizeof(buf), "%s|cus=%d|lb=%u|L=%u|bricks=%u|bytes=%llu|n=%u|lods=%u,%u,%u,%u,%u,%u,%u,%u",
+    snprintf(buf, sizeof(buf), "%s|cus=%d|lb=%u|L=%u|bricks=%u|bytes=%llu|n=%u|lods=%u,%u,%u,%u,%u,%u,%u,%u|I=%d",
              arch.c_str(), device_cus(), p->vol.label_bytes, p->vol.max_log2b, p->vol.n_bricks,
              (unsigned long long)p->vol.total_bytes, n, hist[0], hist[1], hist[2], hist[3], hist[4], hist[5],
-             hist[6], hist[7]);
+             hist[6], hist[7], p->opts.palette_bits);
     return buf;
 }
 

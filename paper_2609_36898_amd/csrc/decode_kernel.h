@@ -63,7 +63,15 @@ struct Params {
     uint8_t* scratch;
     uint64_t scratch_stride;
     uint32_t cap16;     // LDS slots for the explicit nodes of level 5 (>= kMinCap16)
+    uint32_t pal_bits;  // 0: labels; I > 0: packed I-bit palette indices, floor(32/I) per word
 };
+
+// output units of an S^3 cube: labels, or 32-bit words of packed palette indices
+__host__ __device__ inline uint64_t out_units(uint64_t voxels, uint32_t pal_bits) {
+    if (!pal_bits) return voxels;
+    const uint64_t e = 32u / pal_bits;
+    return (voxels + e - 1) / e;
+}
 
 size_t shared_bytes(uint32_t cap16);
 int max_resident_per_cu(int wg_size, uint32_t cap16);  // occupancy of the decode kernel

@@ -188,7 +188,7 @@ __device__ __forceinline__ void parse_task(const Params& P, uint32_t task, TaskH
     if (L < 1 || L > kMaxLog2b || L > P.max_log2b) { h.status = kTaskCorrupt; return; }
     if (lod > L) { h.status = kTaskInvalid; return; }
     const uint32_t t = L - lod;
-    const uint64_t S = 1ull << t, n_out = S * S * S;
+    const uint64_t S = 1ull << t, n_out = out_units(S * S * S, P.pal_bits);
     if (out_off > P.out_cap || n_out > P.out_cap - out_off) { h.status = kTaskInvalid; return; }
     h.write_ok = 1;
     h.L = L;
@@ -237,6 +237,11 @@ __device__ __forceinline__ void parse_task(const Params& P, uint32_t task, TaskH
     const uint32_t need5 = t >= 5 ? h.sym_end[5] - h.sym_end[4] : 0u;
     h.big = pc > 32768u || need5 > P.cap16;
     h.pal_lds = (uint64_t)pc * lb <= kUBytes;
+    // cache-paletted output: a palette beyond 2^I entries, or a 64^3 cube, has no packed form
+    if (P.pal_bits && (t == 6 || (uint64_t)pc > (1ull << P.pal_bits))) {
+        h.status = kTaskInvalid;
+        h.write_ok = 0;
+    }
 }
 
 
@@ -804,9 +809,9 @@ __device__ __forceinline__ void store4(LT* o, LT a, LT b, LT c, LT d, bool vec) 
 template <int NT>
 __device__ __forceinline__ void zero_output(const Params& P, const TaskHdr& h) {
     const uint32_t t = h.t;
-    const uint64_t n = 1ull << (3 * t);
-    uint8_t* out = P.out + h.out_off * P.label_bytes;
-    const uint64_t bytes = n * P.label_bytes;
+    const uint64_t unit = P.pal_bits ? 4u : P.label_bytes;
+    uint8_t* out = P.out + h.out_off * unit;
+    const uint64_t bytes = out_units(1ull << (3 * t), P.pal_bits) * unit;
     if (((uintptr_t)out & 15u) == 0 && (bytes & 15u) == 0) {
         for (uint64_t u = threadIdx.x; u < bytes / 16; u += NT) ((uint4*)out)[u] = make_uint4(0, 0, 0, 0);
     } else {
@@ -887,9 +892,48 @@ __device__ __forceinline__ void write_labels(const Params& P, Shared& sh, const 
     }
 }
 
+// Cache-paletted output: the cube's palette indices, I bits each, floor(32/I)
+// to a 32-bit word (voxel k, x fastest, in word k / e at bit (k mod e) * I).
+// One thread per word; level 5 reaches a voxel's slot through its level-4
+// parent, looked up once per pair of voxels along x.
+template <int NT, typename V>
+__device__ __forceinline__ void write_indices(const Params& P, Shared& sh, const Store<V>& st) {
+    const TaskHdr& h = sh.h;
+    const uint32_t t = h.t, S = 1u << t, bits = P.pal_bits, e = 32u / bits;
+    constexpr uint32_t VIDX = (uint32_t)Slot<V>::kIdx;
+    const uint32_t n = S * S * S, words = (n + e - 1u) / e;
+    uint32_t* const out = (uint32_t*)P.out + h.out_off;
+    for (uint32_t w = threadIdx.x; w < words; w += NT) {
+        uint32_t acc = 0, last_q = 0xFFFFFFFFu, base = 0;
+        bool expands = false;
+        for (uint32_t q = 0; q < e; ++q) {
+            const uint32_t v = w * e + q;
+            if (v >= n) break;
+            const uint32_t x = v & (S - 1u), y = (v >> t) & (S - 1u), z = v >> (2 * t);
+            const uint32_t m = spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+            uint32_t idx;
+            if (t <= 4) {
+                idx = st.full[fbase(t) + m] & VIDX;
+            } else {
+                const uint32_t pq = m >> 3;
+                if (pq != last_q) {
+                    last_q = pq;
+                    expands = st.ebit(4, pq);
+                    base = expands ? 8u * st.rank(4, pq) : (uint32_t)st.full[fbase(4) + pq];
+                }
+                idx = (expands ? (uint32_t)st.c5[base + (m & 7u)] : base) & VIDX;
+            }
+            acc |= idx << (q * bits);
+        }
+        out[w] = acc;
+    }
+}
+
 template <int NT, typename V>
 __device__ __forceinline__ void write_output(const Params& P, Shared& sh, const Store<V>& st) {
-    if (P.label_bytes == 4) {
+    if (P.pal_bits) {
+        write_indices<NT, V>(P, sh, st);
+    } else if (P.label_bytes == 4) {
         if (sh.h.pal_lds) write_labels<NT, V, uint32_t, true>(P, sh, st);
         else write_labels<NT, V, uint32_t, false>(P, sh, st);
     } else {
@@ -923,7 +967,7 @@ __device__ __forceinline__ void run_levels(const Params& P, Shared& sh, uint16_t
     else decode_levels<NT, V, BIG, false>(P, sh, st, nib);
     if (sh.err) return;
     // palette staging for the output pass (the parent list is no longer needed)
-    if (h.pal_lds) {
+    if (h.pal_lds && !P.pal_bits) {
         const uint32_t words = (h.pc * P.label_bytes + 3) / 4;
         const uint32_t* src = (const uint32_t*)(P.vol + h.pal_off);
         for (uint32_t w = threadIdx.x; w < words; w += NT) ((uint32_t*)sh.U)[w] = src[w];
@@ -1071,7 +1115,8 @@ __global__ void __launch_bounds__(256) cost_class_kernel(Params P, uint32_t* cls
     if (j < P.n_tasks) {
         uint64_t rec;
         const uint32_t t = task_t(P, j, &rec);
-        const uint64_t cost = rec + (t <= kMaxLog2b ? ((uint64_t)1 << (3 * t)) * P.label_bytes : 0) + 1;
+        const uint64_t unit = P.pal_bits ? 4u : P.label_bytes;
+        const uint64_t cost = rec + (t <= kMaxLog2b ? out_units((uint64_t)1 << (3 * t), P.pal_bits) * unit : 0) + 1;
         c = 63u - (uint32_t)__clzll(cost);
         cls[j] = c;
     }
@@ -1128,8 +1173,9 @@ __global__ void zero_u32_kernel(uint32_t* p, uint32_t n) {
     if (j < n) p[j] = 0;
 }
 
-// Dense output offsets: exclusive prefix sum of the tasks' cube sizes in task
-// order (a task whose record or LOD is unusable occupies nothing).  One
+// Dense output offsets: exclusive prefix sum of the tasks' cube sizes (labels,
+// or words of packed indices) in task order (a task whose record or LOD is
+// unusable occupies nothing).  One
 // work-group of 1024 threads walks the task list in chunks.
 __global__ void __launch_bounds__(1024) dense_offsets_kernel(Params P, uint64_t* offs) {
     __shared__ uint64_t wsum[16];
@@ -1143,7 +1189,7 @@ __global__ void __launch_bounds__(1024) dense_offsets_kernel(Params P, uint64_t*
         if (j < P.n_tasks) {
             uint64_t rec;
             const uint32_t t = task_t(P, j, &rec);
-            sz = t <= kMaxLog2b ? (1ull << (3 * t)) : 0;
+            sz = t <= kMaxLog2b ? out_units(1ull << (3 * t), P.pal_bits) : 0;
         }
         uint64_t incl = sz;
         for (int d = 1; d < 64; d <<= 1) {

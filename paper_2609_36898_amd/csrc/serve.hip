@@ -128,6 +128,8 @@ csgv_status csgv_server_create(const csgv_volume_info* vol, const void* d_contai
     if (h_brick_log2b) memcpy(l2.data(), h_brick_log2b, vol->n_bricks);
     for (uint8_t v : l2)
         if (v < 1 || v > 6) return serve_fail(CSGV_EINVAL, "brick side exponent outside 1..6");
+    if (cfg && cfg->shape.palette_bits > 0)
+        return serve_fail(CSGV_EINVAL, "the brick cache holds labels (palette_bits must be 0)");
     csgv_server* s = new csgv_server();
     s->be.container = d_container;
     s->be.cache = d_cache;
