@@ -591,8 +591,12 @@ __device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const 
             const uint32_t lo = s0 > j0 ? s0 - j0 : 0u, hi = min(s1 - j0, 1u << lr);
             vm = ((1u << hi) - 1u) & ~((1u << lo) - 1u);
         }
-        RunSum x{0u, 0u, 0u};
-        {
+        // a wave holding no symbol of the level skips its summary, scan and decode
+        // (it still takes part in the barriers and the waves' scan)
+        const bool wave_on = g_first + pg + 64u * wave <= g_last;
+        RunSum incl{kFnId, 0u, 0u}, excl{kFnId, 0u, 0u};
+        if (wave_on) {
+            RunSum x;
             uint32_t e0 = 0, e1 = 1, n0 = 0, n1 = 0, a0 = 0, a1 = 0;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
@@ -607,9 +611,9 @@ __device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const 
                 e1 = vq ? (e1 ? cont : isd) : e1;
             }
             x = RunSum{e0 | (e1 << 1), n0 | (n1 << 16), a0 | (a1 << 16)};
+            incl = wave_scan_run(x);
+            excl = dpp_run<kDppWaveShr1>(incl);
         }
-        const RunSum incl = wave_scan_run(x);
-        const RunSum excl = dpp_run<kDppWaveShr1>(incl);
         if (lane == 63) {
             uint32_t* pub = sh.pub[pb][wave];
             pub[0] = incl.f;
@@ -641,42 +645,103 @@ __device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const 
         carry = (tf >> carry) & 1u;
         pbuf ^= 1u;
         uint32_t ls = (excl.f >> my_e) & 1u;
-        uint32_t k = my_kb + ((excl.n >> (16 * my_e)) & kHalf);
-        uint32_t a = my_ab + ((excl.a >> (16 * my_e)) & kHalf);
-        const uint32_t k_first = k;
+        // this thread's first operation rank and first ADV rank
+        const uint32_t k_first = my_kb + ((excl.n >> (16 * my_e)) & kHalf);
+        const uint32_t a_first = my_ab + ((excl.a >> (16 * my_e)) & kHalf);
         uint32_t opm = 0, refm = 0;
-        for (uint32_t q = 0; q < (1u << lr); ++q) {
-            if (!((vm >> q) & 1u)) continue;
-            const uint32_t sym = (word >> (4 * q)) & 15u;
-            if (ls) {  // a delta entry, read by its operation
-                ls = sym >> 3;
-                continue;
+        if (wave_on) {
+            // classify the thread's symbols from its entry state: operations, and among
+            // them ADVs, palette (ADV, LAST, DELTA, invalid code), parent and neighbour
+            // operations, and stop bits; each kind is then decoded in a loop of its own,
+            // so a wavefront runs one kind's code at a time
+            uint32_t advm = 0, palm = 0, parm = 0, nbm = 0, stopm = 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint32_t sym = (word >> (4 * q)) & 15u, vq = (vm >> q) & 1u, op = sym & 7u;
+                const uint32_t isop = vq & (ls ^ 1u);
+                opm |= isop << q;
+                stopm |= (isop & (sym >> 3)) << q;
+                advm |= (isop & (op == kAdv ? 1u : 0u)) << q;
+                palm |= (isop & (op >= kAdv ? 1u : 0u)) << q;
+                parm |= (isop & (op == kParent ? 1u : 0u)) << q;
+                nbm |= (isop & (op - 1u <= kNZ - 1u ? 1u : 0u)) << q;
+                ls = vq ? (ls ? (sym >> 3) : (op == kDelta ? 1u : 0u)) : ls;
             }
-            const uint32_t op = sym & 7u;
-            ls = op == kDelta;
-            opm |= 1u << q;
-            if (k >= expected) {
+            // operations past the level's node count are an error and write nothing
+            if (k_first + (uint32_t)__popc(opm) > expected) {
                 bad = true;
-                ++k;
-                continue;
+                uint32_t keep = expected > k_first ? expected - k_first : 0u, km = 0;
+                for (uint32_t m = opm; m && keep; m &= m - 1u, --keep) km |= m & (0u - m);
+                palm &= km;
+                parm &= km;
+                nbm &= km;
+                stopm |= ~km;
             }
-            const uint32_t pn = parent_of(k);
-            const uint32_t p = i ? ((pn << 3) | (k & 7u)) : 0u;
-            uint32_t v = FIN;
-            bool is_ref = false, err = false;
-            if (op == kParent) {
-                if (i == 0) err = true;
-                else if (KIND == 2) v = (st.pval_g[k >> 3] & VIDX) | FIN;
-                else v = full_p[pn];
-            } else if (op <= kNZ) {
-                const uint32_t am = op == kNX ? mx : op == kNY ? my : mz;
-                if (!(p & am)) {
+            // rank of the operation at position q, its ADV rank, and its node
+            auto k_at = [&](uint32_t q) -> uint32_t { return k_first + (uint32_t)__popc(opm & ((1u << q) - 1u)); };
+            auto a_at = [&](uint32_t q) -> uint32_t { return a_first + (uint32_t)__popc(advm & ((1u << q) - 1u)); };
+            auto node_of = [&](uint32_t kq) -> uint32_t { return i ? ((parent_of(kq) << 3) | (kq & 7u)) : 0u; };
+            // palette: ADV -> a, LAST -> a - 1, DELTA -> a - delta, the entries following in the window
+            for (uint32_t m = palm; m; m &= m - 1u) {
+                const uint32_t q = (uint32_t)__builtin_ctz(m), kq = k_at(q), aq = a_at(q);
+                const uint32_t op = (word >> (4 * q)) & 7u;
+                uint32_t v = FIN;
+                bool err = false;
+                if (op == kAdv) {
+                    if (aq >= pc) err = true;
+                    else v = FIN | aq;
+                } else if (op == kLast) {
+                    if (aq == 0) err = true;
+                    else v = FIN | (aq - 1u);
+                } else if (op == kDelta) {
+                    uint32_t d = 0, mm = q + 1u, en = 8;
+                    while (en & 8u) {
+                        const uint32_t jj = j0 + mm;
+                        if (jj >= s1) {
+                            err = true;
+                            break;
+                        }
+                        en = mm < avail ? (uint32_t)(win >> (4 * mm)) & 15u : (nib[jj >> 1] >> (4 * (jj & 1))) & 15u;
+                        d = d >= (1u << 29) ? 0xFFFFFFFFu : ((d << 3) | (en & 7u));
+                        ++mm;
+                    }
+                    if (!err) {
+                        if (d == 0 || d > aq) err = true;
+                        else v = FIN | (aq - d);
+                    }
+                } else {
                     err = true;
+                }
+                if (err) {
+                    bad = true;
+                    v = FIN;
+                }
+                // written even after an error, so that a later lookup never meets an unset slot
+                write_slot(slot_of(kq, KIND == 1 ? 0u : node_of(kq)), v);
+            }
+            // parent copies
+            for (uint32_t m = parm; m; m &= m - 1u) {
+                const uint32_t q = (uint32_t)__builtin_ctz(m), kq = k_at(q);
+                const uint32_t pn = parent_of(kq);
+                uint32_t v = FIN;
+                if (i == 0) bad = true;
+                else if (KIND == 2) v = (st.pval_g[kq >> 3] & VIDX) | FIN;
+                else v = full_p[pn];
+                write_slot(slot_of(kq, i ? ((pn << 3) | (kq & 7u)) : 0u), v);
+            }
+            // neighbour copies: an implied target holds its parent's value, an explicit one of
+            // an earlier pass its final value, one of this pass becomes a reference
+            for (uint32_t m = nbm; m; m &= m - 1u) {
+                const uint32_t q = (uint32_t)__builtin_ctz(m), kq = k_at(q);
+                const uint32_t op = (word >> (4 * q)) & 7u;
+                const uint32_t p = node_of(kq);
+                const uint32_t am = op == kNX ? mx : op == kNY ? my : mz;
+                uint32_t v = FIN;
+                if (!(p & am)) {
+                    bad = true;
                 } else {
                     const uint32_t tn = (((p & am) - 1u) & am) | (p & ~am);
                     if (KIND == 0) {
-                        // implied targets hold their parent's value, explicit ones of earlier
-                        // passes their final value, those of this pass "not yet" or a reference
                         v = full_i[tn];
                         if (v == (uint32_t)Slot<V>::kNotYet) v = tn;
                     } else {
@@ -689,48 +754,18 @@ __device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const 
                             v = kt < k0 ? read_slot(ti) : ti;
                         }
                     }
-                    is_ref = !(v & FIN);
+                    refm |= (v & FIN) ? 0u : (1u << q);
                 }
-            } else if (op == kAdv) {
-                if (a >= pc) err = true;
-                else v = FIN | a;
-            } else if (op == kLast) {
-                if (a == 0) err = true;
-                else v = FIN | (a - 1u);
-            } else if (op == kDelta) {
-                // entries follow the operation: in the window, else (long chains) in memory
-                uint32_t d = 0, m = q + 1u, en = 8;
-                while (en & 8u) {
-                    const uint32_t jj = j0 + m;
-                    if (jj >= s1) {
-                        err = true;
-                        break;
-                    }
-                    en = m < avail ? (uint32_t)(win >> (4 * m)) & 15u : (nib[jj >> 1] >> (4 * (jj & 1))) & 15u;
-                    d = d >= (1u << 29) ? 0xFFFFFFFFu : ((d << 3) | (en & 7u));
-                    ++m;
+                write_slot(slot_of(kq, p), v);
+            }
+            // expansion bits of this level's operations without a stop bit
+            if (Ei_l || Ei_g) {
+                for (uint32_t m = opm & ~stopm; m; m &= m - 1u) {
+                    const uint32_t p = node_of(k_at((uint32_t)__builtin_ctz(m)));
+                    if (Ei_l) atomicOr(Ei_l + (p >> 5), 1u << (p & 31));
+                    if (Ei_g) atomicOr(Ei_g + (p >> 5), 1u << (p & 31));
                 }
-                if (!err) {
-                    if (d == 0 || d > a) err = true;
-                    else v = FIN | (a - d);
-                }
-            } else {
-                err = true;
             }
-            if (err) {
-                bad = true;
-                v = FIN;
-                is_ref = false;
-            }
-            // written even after an error, so that a later lookup never meets an unset slot
-            write_slot(slot_of(k, p), v);
-            refm |= (is_ref ? 1u : 0u) << q;
-            if (!(sym & 8u)) {
-                if (Ei_l) atomicOr(Ei_l + (p >> 5), 1u << (p & 31));
-                if (Ei_g) atomicOr(Ei_g + (p >> 5), 1u << (p & 31));
-            }
-            a += op == kAdv;
-            ++k;
         }
         __syncthreads();
         // references within the pass: chase to a final value (targets precede
