@@ -62,7 +62,11 @@ __device__ __forceinline__ uint32_t ebase(uint32_t i) {
 }
 __host__ __device__ constexpr uint32_t ewords(uint32_t i) { return i <= 1 ? 1u : i == 2 ? 2u : (1u << (3 * i - 5)); }
 
+// header words of a record: w0, palette count, sym_end[0..L], up to 4 group word counts
+constexpr uint32_t kHdrWords = 2 + 7 + 4;
+
 struct TaskHdr {
+    uint32_t hw[kHdrWords];  // the record's first words (parse_task)
     uint32_t task, status, write_ok, coder, L, t, log2W, pc, big, pal_lds, nsym;
     uint32_t sym_end[7];
     uint32_t gw[4], gstart[4];
@@ -179,10 +183,18 @@ __device__ __forceinline__ void parse_task(const Params& P, uint32_t task, TaskH
     const uint64_t a = offs[id], b = offs[id + 1];
     if (a > b || b > P.vol_bytes || (a & 7) || b - a < 8) { h.status = kTaskCorrupt; return; }
     const uint8_t* rec = P.vol + a;
-    const uint32_t w0 = ld32(rec);
-    const uint32_t coder = w0 & 0xFF, L = (w0 >> 8) & 0xFF, lb = (w0 >> 16) & 0xFF, log2W = w0 >> 24;
-    const uint32_t pc = ld32(rec + 4);
     const uint64_t extent = b - a;
+    // the record's first kHdrWords words (more than any header holds) are loaded
+    // at once, at offsets clamped into the record; the checks below use a word
+    // only after placing it inside the header
+    {
+        const uint64_t last = (extent & ~3ull) - 4u;
+#pragma unroll
+        for (uint32_t k = 0; k < kHdrWords; ++k) h.hw[k] = ld32(rec + (4u * k < last ? 4u * k : last));
+    }
+    const uint32_t w0 = h.hw[0];
+    const uint32_t coder = w0 & 0xFF, L = (w0 >> 8) & 0xFF, lb = (w0 >> 16) & 0xFF, log2W = w0 >> 24;
+    const uint32_t pc = h.hw[1];
     // (a record larger than every brick the container was parsed with cannot
     // occur for the parsed bytes; it is refused because scratch is sized by them)
     if (L < 1 || L > kMaxLog2b || L > P.max_log2b) { h.status = kTaskCorrupt; return; }
@@ -206,7 +218,7 @@ __device__ __forceinline__ void parse_task(const Params& P, uint32_t task, TaskH
     const uint64_t pay_bytes = extent - pay_rel;
     uint32_t prev = 0;
     for (uint32_t i = 0; i <= L; ++i) {
-        const uint32_t e = ld32(rec + 8 + 4 * i);
+        const uint32_t e = h.hw[2 + i];
         h.sym_end[i] = e;
         if (i > 0 && e < prev) { h.status = kTaskCorrupt; return; }
         prev = e;
@@ -218,7 +230,7 @@ __device__ __forceinline__ void parse_task(const Params& P, uint32_t task, TaskH
         const uint32_t W = 1u << log2W, G = (W + 63) / 64;
         uint64_t tw = 0;
         for (uint32_t g = 0; g < G; ++g) {
-            const uint32_t c = ld32(rec + 8 + 4 * (L + 1) + 4 * g);
+            const uint32_t c = h.hw[3 + L + g];
             h.gw[g] = c;
             h.gstart[g] = (uint32_t)tw;
             tw += c;
@@ -1062,21 +1074,18 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) de
     uint16_t* slots_lds = reinterpret_cast<uint16_t*>(dyn_smem + sizeof(Shared));
     const uint32_t tid = threadIdx.x;
     uint8_t* scratch = P.scratch + (uint64_t)blockIdx.x * P.scratch_stride;
-    uint32_t iter = 0;
+    // thread 0 claims a work-group's next task while the current one is decoded:
+    // the atomic's latency hides behind the decode
+    uint32_t jt = 0;
+    if (tid == 0) jt = P.queue ? atomicAdd(P.queue, 1u) : P.task0 + blockIdx.x;
     for (;;) {
         if (tid == 0) {
-            uint32_t jt;
-            if (P.queue) jt = atomicAdd(P.queue, 1u);
-            else jt = iter == 0 ? P.task0 + blockIdx.x : P.n_tasks;
             sh.err = 0;
-            if (jt < P.n_tasks) {
-                parse_task(P, P.order ? P.order[jt] : jt, sh.h);
-            } else {
-                sh.h.task = 0xFFFFFFFFu;
-            }
+            if (jt < P.n_tasks) parse_task(P, P.order ? P.order[jt] : jt, sh.h);
+            else sh.h.task = 0xFFFFFFFFu;
         }
         __syncthreads();
-        ++iter;
+        if (tid == 0) jt = P.queue && jt < P.n_tasks ? atomicAdd(P.queue, 1u) : P.n_tasks;
         const uint32_t task = sh.h.task;
         if (task == 0xFFFFFFFFu) break;
         decode_task<NT>(P, sh, slots_lds, scratch);
