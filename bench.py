@@ -240,12 +240,7 @@ def measure(wl: Workload, args, dev):
     }
 
     if args.calib_copy:
-        src = torch.empty(CALIB_COPY_BYTES // 4, dtype=torch.int32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        calib_copy(dev)
 
     if wl.plain and not args.no_plain:
         plain_out = torch.empty_like(out)
@@ -276,6 +271,17 @@ def measure(wl: Workload, args, dev):
     del out, status, dv
     torch.cuda.empty_cache()
     return res
+
+
+def calib_copy(dev):
+    """Device copies of CALIB_COPY_BYTES: the reference kernel for HBM counter scaling."""
+    import torch
+    src = torch.empty(CALIB_COPY_BYTES // 4, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def measure_paletted(wl: Workload, args, dev, shape):
@@ -361,6 +367,8 @@ def measure_served(wl: Workload, args, dev):
     import paper_2609_36898_amd as P
     from synth import workloads as W
     dv = P.DeviceVolume(wl.container, device=dev)
+    if args.calib_copy:
+        calib_copy(dev)
     cache_elems = SERVE_CACHE_BYTES // 4
     cache = torch.empty(cache_elems, dtype=torch.int32, device=dev)
     nw, nm = args.serve_warmup, args.serve_requests
@@ -449,7 +457,9 @@ def measure_served(wl: Workload, args, dev):
                      "frac": round(kgbs / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(wl.name),
                      "kernel": DECODE_KERNEL, "kernel_ms_total": round(sat_d["kernel_ms"], 3),
                      "launches": sat_d["batches"], "alg_bytes_total": alg,
-                     "note": "over the saturation run: sum of algorithmic bytes / sum of decode-kernel times"},
+                     "alg_bytes_per_launch": round(alg / max(sat_d["batches"], 1), 1),
+                     "note": "over the saturation run: sum of algorithmic bytes / sum of decode-kernel times; "
+                             "traffic = mean HBM bytes per decode dispatch of a profiled served run"},
         "served": {"saturation": sat, **loads, "checked_requests": len(check), "checked_pairs": int(len(c_ids))},
         "bit_exact": exact and sat["all_ok"] and all(v["all_ok"] for v in loads.values()),
         "shape": {"wg_size": "default", "sort_tasks": "default"},
