@@ -172,3 +172,17 @@ def test_random_traces_keep_every_invariant(sim):
         assert s["requests_done"] == int((st == 0).sum())
         assert s["hits"] + s["joined"] + s["decoded"] == s["pairs_requested"]
         assert s["pinned"] == 0 and s["top"] <= cache
+
+
+def test_eviction_follows_least_recent_use(sim):
+    # three full bricks fill the cache; a hit on brick 0 makes brick 1 the least
+    # recently used, so brick 3 evicts brick 1 and brick 0 stays resident
+    l2 = np.full(8, 5, np.uint8)
+    ids = np.array([0, 1, 2, 0, 3, 0, 1], np.uint32)
+    lods = np.zeros(7, np.uint8)
+    starts = np.array([0, 3, 4, 5, 6, 7], np.uint64)
+    arr = np.array([0.0, 1.0, 2.0, 3.0, 4.0])
+    _, _, st, ndec, s = run(sim, l2, 3 * 32 ** 3, ids, lods, starts, arr, delay=2)
+    assert (st == 0).all()
+    assert list(ndec) == [3, 0, 1, 0, 1]
+    assert s["evictions"] == 2 and s["resets"] == 0
