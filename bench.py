@@ -470,6 +470,70 @@ def measure_served(wl: Workload, args, dev):
     return res
 
 
+ABLATION = [("adv", 0), ("+parent", 1), ("+nx", 3), ("+ny", 7), ("+nz", 15), ("+last", 31), ("+delta", 63),
+            ("+delta<=16", 127)]
+
+
+def op_ablation(args, dev):
+    """Operation-set ablation: every prefix of PARENT, NX, NY, NZ, LAST, DELTA
+    (ADV always on) and DELTA limited to 16 entries, on voronoi512 (LOD 0) and
+    neurite1024 (its LOD mix): compressed bytes, bits per voxel, palette
+    lengths and duplicates, and batched decode GVoxel/s (default shape), each
+    run bit-exact against the raw volume or the CPU oracle."""
+    import torch
+    import oracle
+    import paper_2609_36898_amd as P
+    from synth import workloads as W
+    rows = []
+    for name in ("voronoi512", "neurite1024"):
+        vol = W.voronoi512() if name == "voronoi512" else W.neurite1024()
+        n_b = (vol.shape[0] // 32) ** 3
+        lods = np.zeros(n_b, np.uint8) if name == "voronoi512" else W.neurite1024_lods(n_b)
+        raw = P.bricks_of_volume(vol, 5) if name == "voronoi512" else None
+        for label, mask in ABLATION:
+            t0 = time.time()
+            c = P.encode_volume(vol, 5, op_mask=mask)
+            enc_s = time.time() - t0
+            info = P.csgv_volume_parse(c)
+            pals = np.array([int(np.frombuffer(c, np.uint32, count=1, offset=int(o) + 4)[0])
+                             for o in np.frombuffer(c, np.uint64, count=n_b, offset=int(info.offsets_pos))])
+            dv = P.DeviceVolume(c, device=dev)
+            ids = np.arange(n_b, dtype=np.uint32)
+            d_ids, d_lods, d_offs, offs, total = dv.tasks(ids, lods, dev)
+            out = torch.empty(total, dtype=dv.dtype, device=dev)
+            status = torch.full((n_b,), -1, dtype=torch.int32, device=dev)
+            plan = P.csgv_plan(dv.info, n_b)
+            stream = torch.cuda.current_stream(dev)
+            for _ in range(args.warmup):
+                plan.launch(stream, dv.tensor, d_ids, d_lods, d_offs, n_b, out, total, status)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                plan.launch(stream, dv.tensor, d_ids, d_lods, d_offs, n_b, out, total, status)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            plan.destroy()
+            got = out.cpu().numpy().view(np.uint32)
+            if raw is not None:
+                exact = bool(np.array_equal(got, raw))
+            else:
+                want, wst = oracle.decode_tasks(c, ids, lods, offs, total, 4, nthreads=cpu_threads())
+                exact = bool(np.array_equal(got, want)) and bool((wst == 0).all())
+            exact = exact and bool((status == 0).all().item())
+            del out, dv
+            torch.cuda.empty_cache()
+            row = {"workload": name, "ops": label, "op_mask": mask, "compressed_bytes": len(c),
+                   "bits_per_voxel": round(8.0 * len(c) / vol.size, 4), "palette_mean": round(float(pals.mean()), 2),
+                   "palette_max": int(pals.max()), "decode_gvoxel_s": round(total / (ms * 1e-3) / 1e9, 2) if exact else None,
+                   "ms_per_step": round(ms, 4), "bit_exact": exact, "encode_s": round(enc_s, 2)}
+            _log(json.dumps(row))
+            rows.append(row)
+        del vol
+    return rows
+
+
 def cpu_baseline_served(wl: Workload, ids, lods, starts):
     """The oracle decoding every pair of the first measured requests (about
     1/20 of the trace's pairs, cache hits included) on all host cores."""
@@ -628,6 +692,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain one-launch-per-brick legs")
     ap.add_argument("--no-tune", action="store_true", help="default launch shape instead of the autotuner")
     ap.add_argument("--no-paletted", action="store_true", help="skip the cache-paletted leg of neurite1024")
+    ap.add_argument("--ablation", action="store_true",
+                    help="operation-set ablation (compressed size and decode GVoxel/s per op prefix) instead")
     ap.add_argument("--tune-cache", default=os.environ.get("CSGV_TUNE_CACHE", "/tmp/csgv_autotune.txt"))
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run device-to-device copies of CALIB_COPY_BYTES (reference kernel for HBM counter scaling)")
@@ -644,6 +710,12 @@ def main():
         return
     if args.summarize_rocprof:
         sys.stdout.write(summarize_rocprof(args.summarize_rocprof, (args.workload or [HEADLINE])[0]))
+        return
+    if args.ablation:
+        import torch
+        dev = torch.device("cuda:0")
+        rows = op_ablation(args, dev)
+        print(json.dumps({"op_ablation": rows, "kernel_source": kernel_source_hash()}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the decode path has no multi-GPU form in this build (bricks are "

@@ -357,7 +357,11 @@ void csgv_server_destroy(csgv_server* server);
  *   dims, grid     informational volume size and brick grid (may be NULL).
  *   h_origins      n_bricks x 3 voxel origins for the directory, or NULL.
  *   op_mask        bit0 PARENT, bit1 NEIGHBOR_X, bit2 NEIGHBOR_Y, bit3 NEIGHBOR_Z,
- *                  bit4 PALETTE_LAST, bit5 PALETTE_DELTA (PALETTE_ADV is always on).
+ *                  bit4 PALETTE_LAST, bit5 PALETTE_DELTA (PALETTE_ADV is always on);
+ *                  bit6 limits PALETTE_DELTA to back references of at most 16 entries
+ *                  (the original format's limit; labels further back are appended again,
+ *                  which duplicates palette entries -- Methods > "Memory management" >
+ *                  "Cache paletting").
  *   neighbor_mode  0: neighbour copies at any position; 1: only across sibling groups.
  *   coder_policy   0: per brick the smaller of plain 4-bit and rANS; 1: plain; 2: rANS.
  *   lane_syms      target symbols per rANS lane (sets the lane count W <= 256).

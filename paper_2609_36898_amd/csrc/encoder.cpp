@@ -108,6 +108,8 @@ struct Worker {
     PosTable pos;
 };
 
+constexpr uint32_t kLegacyDelta = 16;  // longest palette back reference with op_mask bit 6
+
 void encode_brick(const uint8_t* vox, uint32_t lb, uint32_t L, uint32_t op_mask, uint32_t nmode, Worker& w,
                   BrickCode& out) {
     const uint32_t b = 1u << L;
@@ -183,7 +185,9 @@ void encode_brick(const uint8_t* vox, uint32_t lb, uint32_t L, uint32_t op_mask,
             if (op == kBadOp && (op_mask & 16u) && !out.pal.empty() && out.pal.back() == v) op = kLast;
             if (op == kBadOp && (op_mask & 32u)) {
                 uint32_t p;
-                if (w.pos.find(v, &p)) {
+                // bit 6: back references of at most kLegacyDelta entries, as in the original
+                // format; a label further back is appended again (a palette duplicate)
+                if (w.pos.find(v, &p) && (!(op_mask & 64u) || out.pal.size() - p <= kLegacyDelta)) {
                     op = kDelta;
                     delta = (uint32_t)out.pal.size() - p;
                 }

@@ -139,3 +139,37 @@ def test_streaming_encoder_matches_one_shot(P):
         enc.add(flat[k0 * per:k1 * per], [5] * (k1 - k0))
     assert enc.finish() == whole
     enc.destroy()
+
+
+def _max_delta(sym):
+    """Largest palette back reference in a symbol stream (sequential walk)."""
+    best, j = 0, 0
+    while j < len(sym):
+        s = int(sym[j])
+        j += 1
+        if (s & 7) == 6:
+            d, e = 0, 8
+            while e & 8:
+                e = int(sym[j])
+                j += 1
+                d = (d << 3) | (e & 7)
+            best = max(best, d)
+    return best
+
+
+def test_legacy_back_reference_limit(P):
+    # op_mask bit 6: DELTA only within 16 palette entries; labels further back are
+    # appended again, so palettes carry duplicates; decoding is unchanged
+    rng = np.random.default_rng(7)
+    brick = rng.integers(1, 40, size=(16, 16, 16), dtype=np.uint64).astype(np.uint32)
+    for mask, limited in ((63, False), (127, True)):
+        c = P.csgv_encode_bricks(brick.reshape(-1), [4], 4, op_mask=mask)
+        sym, se, info = oracle.record_symbols(c, 0)
+        pal = oracle.record_palette(c, 0)
+        md = _max_delta(sym)
+        if limited:
+            assert md <= 16 and len(pal) > len(set(pal.tolist()))
+        else:
+            assert md > 16 and len(pal) == len(set(pal.tolist()))
+        out, st = oracle.decode_tasks(c, [0], [0], [0], 4096, 4)
+        assert st[0] == 0 and np.array_equal(out, brick.reshape(-1))

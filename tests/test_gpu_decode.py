@@ -92,7 +92,7 @@ def test_coders_and_mixed_lods(P, policy):
 
 def test_op_masks_and_neighbor_modes(P):
     v = synth.neurite_u32(128, 200, seed=4)
-    for mask in (0, 1, 15, 31, 63):
+    for mask in (0, 1, 15, 31, 63, 127):  # 127: back references limited to 16 entries (palette duplicates)
         for nm in (0, 1):
             c = P.encode_volume(v, 5, op_mask=mask, neighbor_mode=nm)
             _compare(P, c, np.arange(64), np.arange(64) % 4, modes=(2,))
