@@ -383,7 +383,7 @@ def measure_served(wl: Workload, args, dev):
 
     def run(rate):
         srv = P.csgv.csgv_server(dv.info, dv.tensor, cache, cache_elems, n_streams=args.serve_streams,
-                                 max_batch=args.serve_batch)
+                                 max_batch=args.serve_batch, n_shards=args.serve_shards)
         srv.run(ids[:sw], lods[:sw], starts[:nw + 1], np.zeros(nw))
         s0 = srv.stats()
         arr = np.zeros(nm) if rate is None else (unit_arr[nw:] - unit_arr[nw]) / rate
@@ -421,7 +421,7 @@ def measure_served(wl: Workload, args, dev):
     sizes = np.diff(m_starts.astype(np.int64))
     check = [r for r in range(n_req) if sizes[r] <= 1024][:args.serve_check]
     srv = P.csgv.csgv_server(dv.info, dv.tensor, cache, cache_elems, n_streams=args.serve_streams,
-                             max_batch=args.serve_batch, keep_pinned=True)
+                             max_batch=args.serve_batch, keep_pinned=True, n_shards=args.serve_shards)
     exact = True
     c_ids, c_lods, c_got = [], [], []
     for r in check:
@@ -452,7 +452,7 @@ def measure_served(wl: Workload, args, dev):
     res = {
         "value": sat["decoded_gvoxel_s"], "ms_per_step": round(1e3 * sat["seconds"] / nm, 4),
         "config": dict(wl.config, warmup_requests=nw, measured_requests=nm, lod_histogram=lod_hist,
-                       streams=args.serve_streams, max_batch=args.serve_batch),
+                       streams=args.serve_streams, max_batch=args.serve_batch, shards=args.serve_shards),
         "roofline": {"bound": "hbm", "achieved": round(kgbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(kgbs / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(wl.name),
                      "kernel": DECODE_KERNEL, "kernel_ms_total": round(sat_d["kernel_ms"], 3),
@@ -699,7 +699,8 @@ def main():
                     help="also run device-to-device copies of CALIB_COPY_BYTES (reference kernel for HBM counter scaling)")
     ap.add_argument("--serve-requests", type=int, default=10000, help="measured requests of the served workload")
     ap.add_argument("--serve-warmup", type=int, default=1000, help="warm-up requests before each served run")
-    ap.add_argument("--serve-streams", type=int, default=3)
+    ap.add_argument("--serve-streams", type=int, default=2, help="HIP streams per cache shard")
+    ap.add_argument("--serve-shards", type=int, default=8, help="cache shards (host threads) of the server")
     ap.add_argument("--serve-batch", type=int, default=4096)
     ap.add_argument("--serve-check", type=int, default=24, help="pinned requests checked against the oracle")
     ap.add_argument("--summarize-rocprof", default=None, metavar="DIR")

@@ -289,8 +289,16 @@ csgv_status csgv_plan_autotune(csgv_plan* plan, hipStream_t stream, const void* 
  *  - A completed request's pairs stay pinned (their cache contents cannot
  *    change) until the next csgv_server_step, or with keep_pinned until
  *    csgv_server_release.
+ *  - Shards (n_shards > 1): brick b belongs to shard b mod n_shards, which
+ *    owns an equal, contiguous range of the cache, its own n_streams streams
+ *    and its own LRU lists; every request is split into one part per shard.
+ *    A request completes when its last part does (admission and completion
+ *    times are the latest over its parts, pair counts the sums, status -1 if
+ *    a part is rejected).  Admission is in arrival order within a shard.
+ *    csgv_server_run serves the shards from one host thread each.
  * h_brick_log2b: side exponent per brick (n_bricks entries), or NULL for
- * vol->log2b everywhere.  One server is driven by one host thread.
+ * vol->log2b everywhere.  Calls on one server come from one host thread at a
+ * time.
  */
 typedef struct csgv_server csgv_server;
 
@@ -299,6 +307,8 @@ typedef struct {
     uint32_t max_batch;       /* tasks per batch, default 4096 */
     int keep_pinned;          /* completed requests stay pinned until csgv_server_release */
     csgv_decode_opts shape;   /* launch shape of every batch (fields 0 / -1 = defaults) */
+    int n_shards;             /* cache shards (host threads in csgv_server_run), default 1, at most 16;
+                                 each holds floor(cache_elements / n_shards) rounded down to 64 elements */
 } csgv_server_config;
 
 typedef struct {

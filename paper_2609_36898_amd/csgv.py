@@ -310,7 +310,7 @@ class csgv_encoder:
 # ------------------------------------------------------------------ serving
 class ServerConfig(ctypes.Structure):
     _fields_ = [("n_streams", ctypes.c_int), ("max_batch", ctypes.c_uint32), ("keep_pinned", ctypes.c_int),
-                ("shape", DecodeOpts)]
+                ("shape", DecodeOpts), ("n_shards", ctypes.c_int)]
 
 
 class RequestDone(ctypes.Structure):
@@ -367,11 +367,11 @@ class csgv_server:
 
     def __init__(self, vol: VolumeInfo, d_container, d_cache, cache_elements: int, brick_log2b=None,
                  n_streams: int = 2, max_batch: int = 4096, keep_pinned: bool = False, wg_size: int = 0,
-                 lds_slots: int = 0, sort_tasks: int = -1):
+                 lds_slots: int = 0, sort_tasks: int = -1, n_shards: int = 1):
         self._h = ctypes.c_void_p()
         self._l2 = None if brick_log2b is None else np.ascontiguousarray(np.asarray(brick_log2b, dtype=np.uint8))
         cfg = ServerConfig(n_streams, max_batch, int(keep_pinned),
-                           DecodeOpts(MODE_PERSISTENT, wg_size, 0, sort_tasks, 0, lds_slots, 0))
+                           DecodeOpts(MODE_PERSISTENT, wg_size, 0, sort_tasks, 0, lds_slots, 0), n_shards)
         _scheck(_lib.csgv_server_create(ctypes.byref(vol), _ptr(d_container),
                                         None if self._l2 is None else self._l2.ctypes.data, _ptr(d_cache),
                                         cache_elements, ctypes.byref(cfg), ctypes.byref(self._h)),

@@ -1,10 +1,13 @@
 // Served decode: the host scheduler of serve_core.h driving batched decode
-// plans on several HIP streams, and its C ABI.
+// plans on several HIP streams, and its C ABI.  The cache may be split into
+// brick shards (ShardSet), each with its own streams and plans, served by one
+// host thread each in csgv_server_run.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <string>
 #include <thread>
 #include <vector>
@@ -35,8 +38,9 @@ struct GpuBackend {
     uint64_t cache_elems = 0;
     hipError_t err = hipSuccess;
     csgv_status plan_err = CSGV_OK;
+    std::string plan_msg;  // the plan's error message (read on the thread that launched)
     uint64_t failed_tasks = 0;
-    std::vector<uint64_t> rec_off;  // host copy of the container's record offsets
+    const uint64_t* rec_off = nullptr;  // host copy of the container's record offsets
     uint64_t record_bytes = 0;
     double kernel_ms = 0;
 
@@ -67,7 +71,10 @@ struct GpuBackend {
             const csgv_status st = csgv_plan_launch(l.plan, l.stream, container, (const uint32_t*)(l.d_tasks + 8ull * n),
                                                     l.d_tasks + 12ull * n, (const uint64_t*)l.d_tasks, n, cache,
                                                     cache_elems, l.d_status);
-            if (st != CSGV_OK && plan_err == CSGV_OK) plan_err = st;
+            if (st != CSGV_OK && plan_err == CSGV_OK) {
+                plan_err = st;
+                plan_msg = csgv_last_error();
+            }
         }
         if (e == hipSuccess) e = hipMemcpyAsync(l.h_status, l.d_status, 4ull * n, hipMemcpyDeviceToHost, l.stream);
         if (e == hipSuccess) e = hipEventRecord(l.done, l.stream);
@@ -80,8 +87,9 @@ thread_local std::string g_serve_error;
 }  // namespace
 
 struct csgv_server {
-    GpuBackend be;
-    csgv::Scheduler<GpuBackend>* sched = nullptr;
+    std::vector<std::unique_ptr<GpuBackend>> be;  // one per shard
+    std::vector<uint64_t> rec_off;                 // the container's record offsets (host copy)
+    csgv::ShardSet<GpuBackend>* sched = nullptr;
     std::chrono::steady_clock::time_point t0;
     std::deque<csgv::ServeDone> done;  // completions not yet drained
 };
@@ -93,9 +101,13 @@ csgv_status serve_fail(csgv_status s, const char* msg) {
     return s;
 }
 
+bool backend_ok(const GpuBackend& b) { return b.err == hipSuccess && b.plan_err == CSGV_OK; }
+
 csgv_status backend_status(csgv_server* s) {
-    if (s->be.err != hipSuccess) return serve_fail(CSGV_EHIP, hipGetErrorString(s->be.err));
-    if (s->be.plan_err != CSGV_OK) return serve_fail(s->be.plan_err, csgv_last_error());
+    for (auto& b : s->be) {
+        if (b->err != hipSuccess) return serve_fail(CSGV_EHIP, hipGetErrorString(b->err));
+        if (b->plan_err != CSGV_OK) return serve_fail(b->plan_err, b->plan_msg.c_str());
+    }
     return CSGV_OK;
 }
 
@@ -113,6 +125,12 @@ void destroy_lanes(GpuBackend& be) {
     be.lanes.clear();
 }
 
+void destroy_server(csgv_server* s) {
+    for (auto& b : s->be) destroy_lanes(*b);
+    delete s->sched;
+    delete s;
+}
+
 }  // namespace
 
 extern "C" {
@@ -123,7 +141,12 @@ csgv_status csgv_server_create(const csgv_volume_info* vol, const void* d_contai
     if (!vol || !d_container || !d_cache || !out || cache_elements == 0) return serve_fail(CSGV_EINVAL, "NULL argument");
     const int n_streams = cfg && cfg->n_streams > 0 ? cfg->n_streams : 2;
     const uint32_t max_batch = cfg && cfg->max_batch > 0 ? cfg->max_batch : 4096;
+    const uint32_t n_shards = cfg && cfg->n_shards > 0 ? (uint32_t)cfg->n_shards : 1u;
     if (n_streams > 16) return serve_fail(CSGV_EINVAL, "at most 16 streams");
+    if (n_shards > 16) return serve_fail(CSGV_EINVAL, "at most 16 shards");
+    // equal shard ranges, 64-element aligned
+    const uint64_t share = n_shards == 1 ? cache_elements : (cache_elements / n_shards) & ~uint64_t(63);
+    if (share == 0) return serve_fail(CSGV_EINVAL, "cache too small for the shard count");
     std::vector<uint8_t> l2(vol->n_bricks, (uint8_t)vol->log2b);
     if (h_brick_log2b) memcpy(l2.data(), h_brick_log2b, vol->n_bricks);
     for (uint8_t v : l2)
@@ -131,45 +154,53 @@ csgv_status csgv_server_create(const csgv_volume_info* vol, const void* d_contai
     if (cfg && cfg->shape.palette_bits > 0)
         return serve_fail(CSGV_EINVAL, "the brick cache holds labels (palette_bits must be 0)");
     csgv_server* s = new csgv_server();
-    s->be.container = d_container;
-    s->be.cache = d_cache;
-    s->be.cache_elems = cache_elements;
+    // record offsets (the parsed volume guarantees they lie inside the container)
+    s->rec_off.resize((size_t)vol->n_bricks + 1);
+    if (hipMemcpy(s->rec_off.data(), (const uint8_t*)d_container + vol->offsets_pos, 8ull * (vol->n_bricks + 1),
+                  hipMemcpyDeviceToHost) != hipSuccess) {
+        destroy_server(s);
+        return serve_fail(CSGV_EHIP, "reading the record offsets");
+    }
     csgv_decode_opts o;
     memset(&o, 0, sizeof(o));
     if (cfg) o = cfg->shape;
     else o.sort_tasks = -1;
     o.mode = CSGV_MODE_PERSISTENT;
-    s->be.lanes.resize(n_streams);
-    for (auto& l : s->be.lanes) {
-        if (hipStreamCreateWithFlags(&l.stream, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&l.done, hipEventDisableTiming) != hipSuccess ||
-            hipHostMalloc((void**)&l.h_tasks, 13ull * max_batch, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc((void**)&l.h_status, 4ull * max_batch, hipHostMallocDefault) != hipSuccess ||
-            hipMalloc((void**)&l.d_tasks, 13ull * max_batch) != hipSuccess ||
-            hipMalloc((void**)&l.d_status, 4ull * max_batch) != hipSuccess) {
-            destroy_lanes(s->be);
-            delete s;
-            return serve_fail(CSGV_ENOMEM, "server stream resources");
+    std::vector<GpuBackend*> bes;
+    std::vector<uint64_t> base, cap;
+    for (uint32_t w = 0; w < n_shards; ++w) {
+        s->be.emplace_back(new GpuBackend());
+        GpuBackend& be = *s->be.back();
+        be.container = d_container;
+        be.cache = (uint8_t*)d_cache + (uint64_t)w * share * vol->label_bytes;
+        be.cache_elems = share;
+        be.rec_off = s->rec_off.data();
+        be.lanes.resize(n_streams);
+        for (auto& l : be.lanes) {
+            if (hipStreamCreateWithFlags(&l.stream, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&l.done, hipEventDisableTiming) != hipSuccess ||
+                hipHostMalloc((void**)&l.h_tasks, 13ull * max_batch, hipHostMallocDefault) != hipSuccess ||
+                hipHostMalloc((void**)&l.h_status, 4ull * max_batch, hipHostMallocDefault) != hipSuccess ||
+                hipMalloc((void**)&l.d_tasks, 13ull * max_batch) != hipSuccess ||
+                hipMalloc((void**)&l.d_status, 4ull * max_batch) != hipSuccess) {
+                destroy_server(s);
+                return serve_fail(CSGV_ENOMEM, "server stream resources");
+            }
+            const csgv_status st = csgv_plan_create(vol, max_batch, &o, &l.plan);
+            if (st != CSGV_OK) {
+                const std::string msg = csgv_last_error();
+                destroy_server(s);
+                return serve_fail(st, msg.c_str());
+            }
+            (void)csgv_plan_set_graph(l.plan, 0);  // batches differ in size: direct launches
+            (void)csgv_plan_set_timing(l.plan, 1);
         }
-        const csgv_status st = csgv_plan_create(vol, max_batch, &o, &l.plan);
-        if (st != CSGV_OK) {
-            destroy_lanes(s->be);
-            delete s;
-            return serve_fail(st, csgv_last_error());
-        }
-        (void)csgv_plan_set_graph(l.plan, 0);  // batches differ in size: direct launches
-        (void)csgv_plan_set_timing(l.plan, 1);
+        bes.push_back(&be);
+        base.push_back((uint64_t)w * share);
+        cap.push_back(share);
     }
-    // record offsets (the parsed volume guarantees they lie inside the container)
-    s->be.rec_off.resize((size_t)vol->n_bricks + 1);
-    if (hipMemcpy(s->be.rec_off.data(), (const uint8_t*)d_container + vol->offsets_pos, 8ull * (vol->n_bricks + 1),
-                  hipMemcpyDeviceToHost) != hipSuccess) {
-        destroy_lanes(s->be);
-        delete s;
-        return serve_fail(CSGV_EHIP, "reading the record offsets");
-    }
-    s->sched = new csgv::Scheduler<GpuBackend>(s->be, cache_elements, l2.data(), vol->n_bricks, max_batch,
-                                               cfg && cfg->keep_pinned);
+    s->sched = new csgv::ShardSet<GpuBackend>(bes, base, cap, l2.data(), vol->n_bricks, max_batch,
+                                              cfg && cfg->keep_pinned);
     s->t0 = std::chrono::steady_clock::now();
     *out = s;
     return CSGV_OK;
@@ -226,46 +257,24 @@ csgv_status csgv_server_run(csgv_server* s, const uint32_t* h_ids, const uint8_t
         if (h_req_start[r + 1] < h_req_start[r]) return serve_fail(CSGV_EINVAL, "request starts not ordered");
         if (r && h_arrival[r] < h_arrival[r - 1]) return serve_fail(CSGV_EINVAL, "arrivals not ordered");
     }
-    const double base = csgv_server_clock(s);
-    std::vector<uint64_t> ids(n_req);
-    uint32_t next = 0, done = 0;
-    uint64_t first = 0;
-    while (done < n_req) {
-        // requests are handed to the scheduler as they arrive
-        const double now = csgv_server_clock(s);
-        for (; next < n_req && base + h_arrival[next] <= now; ++next) {
-            const uint64_t a = h_req_start[next], b = h_req_start[next + 1];
-            if (!s->sched->submit(h_ids + a, h_lods + a, (uint32_t)(b - a), base + h_arrival[next], &ids[next]))
-                return serve_fail(CSGV_EINVAL, "a pair names no brick, or a LOD beyond the brick side");
-            if (next == 0) first = ids[0];
-        }
-        s->sched->step(csgv_server_clock(s));
+    if (n_req && (!h_ids || !h_lods) && h_req_start[n_req] > h_req_start[0]) return serve_fail(CSGV_EINVAL, "NULL pairs");
+    if (n_req && !s->sched->valid(h_ids + h_req_start[0], h_lods + h_req_start[0], h_req_start[n_req] - h_req_start[0]))
+        return serve_fail(CSGV_EINVAL, "a pair names no brick, or a LOD beyond the brick side");
+    static_assert(sizeof(csgv_request_done) == sizeof(csgv::ServeDone), "layouts agree");
+    const bool ok = s->sched->run(
+        h_ids, h_lods, h_req_start, n_req, h_arrival, csgv_server_clock(s), [s] { return csgv_server_clock(s); },
+        [s](uint32_t w) { return backend_ok(*s->be[w]); }, reinterpret_cast<csgv::ServeDone*>(out));
+    for (const csgv::ServeDone& d : s->sched->take_early()) s->done.push_back(d);
+    if (!ok) {
         const csgv_status st = backend_status(s);
-        if (st != CSGV_OK) return st;
-        for (const csgv::ServeDone& d : s->sched->drain()) {
-            const uint64_t r = d.req - first;
-            if (next > 0 && d.req >= first && r < n_req) {
-                memcpy(&out[r], &d, sizeof(d));
-                out[r].t_arrival -= base;
-                out[r].t_admit -= base;
-                out[r].t_done -= base;
-                ++done;
-            } else {
-                s->done.push_back(d);  // a request submitted outside this run
-            }
-        }
-        // idle until the next arrival when nothing is waiting, queued or in flight
-        if (s->sched->in_flight() == 0 && next < n_req && s->sched->next_arrival() < 0) {
-            const double na = base + h_arrival[next], t = csgv_server_clock(s);
-            if (na > t + 2e-4) std::this_thread::sleep_for(std::chrono::duration<double>(na - t - 1e-4));
-        }
+        return st != CSGV_OK ? st : serve_fail(CSGV_EHIP, "served run stopped");
     }
     return CSGV_OK;
 }
 
 csgv_status csgv_server_get_stats(csgv_server* s, csgv_server_stats* out) {
     if (!s || !out) return serve_fail(CSGV_EINVAL, "NULL argument");
-    const csgv::ServeStats& t = s->sched->stats();
+    const csgv::ServeStats t = s->sched->stats();
     out->requests_done = t.requests_done;
     out->pairs_requested = t.pairs_requested;
     out->hits = t.hits;
@@ -279,10 +288,15 @@ csgv_status csgv_server_get_stats(csgv_server* s, csgv_server_stats* out) {
     out->cache_top = t.top;
     out->resident = t.resident;
     out->pinned = t.pinned;
-    out->failed_tasks = s->be.failed_tasks;
+    out->failed_tasks = 0;
+    out->record_bytes = 0;
+    out->kernel_ms = 0;
+    for (auto& b : s->be) {
+        out->failed_tasks += b->failed_tasks;
+        out->record_bytes += b->record_bytes;
+        out->kernel_ms += b->kernel_ms;
+    }
     out->splits = t.splits;
-    out->record_bytes = s->be.record_bytes;
-    out->kernel_ms = s->be.kernel_ms;
     out->max_batch_seen = t.max_batch_seen;
     return CSGV_OK;
 }
@@ -290,10 +304,7 @@ csgv_status csgv_server_get_stats(csgv_server* s, csgv_server_stats* out) {
 const char* csgv_server_last_error(void) { return g_serve_error.c_str(); }
 
 void csgv_server_destroy(csgv_server* s) {
-    if (!s) return;
-    destroy_lanes(s->be);
-    delete s->sched;
-    delete s;
+    if (s) destroy_server(s);
 }
 
 }  // extern "C"

@@ -31,7 +31,11 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <deque>
+#include <memory>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -57,10 +61,13 @@ class Scheduler {
 public:
     static constexpr uint32_t kClasses = 7;  // cube sides 1 .. 64
 
-    // brick_log2b: side exponent of every brick (1..6)
+    // brick_log2b: side exponent of every brick (1..6).  Batches name brick
+    // i * id_stride + id_offset for the scheduler's brick i (a shard of a
+    // larger volume, see ShardSet).
     Scheduler(Backend& be, uint64_t cache_elems, const uint8_t* brick_log2b, uint32_t n_bricks, uint32_t max_batch,
-              bool keep_pinned)
-        : be_(be), cap_(cache_elems), max_batch_(max_batch ? max_batch : 1), keep_pinned_(keep_pinned) {
+              bool keep_pinned, uint32_t id_stride = 1, uint32_t id_offset = 0)
+        : be_(be), cap_(cache_elems), max_batch_(max_batch ? max_batch : 1), keep_pinned_(keep_pinned),
+          id_stride_(id_stride), id_offset_(id_offset) {
         l2_.assign(brick_log2b, brick_log2b + n_bricks);
         slot_.assign((size_t)n_bricks * 8, 0u);
         stamp_.assign((size_t)n_bricks * 8, 0u);
@@ -392,7 +399,7 @@ private:
             Entry& e = ent_[slot_[k] - 1];
             e.state = kFlight;
             b.push_back(k);
-            ids_.push_back((uint32_t)(k >> 3));
+            ids_.push_back((uint32_t)(k >> 3) * id_stride_ + id_offset_);
             lods_.push_back((uint8_t)(k & 7));
             offs_.push_back(e.off);
             st_.decoded_elements += cls_elems_[e.cls];
@@ -440,6 +447,7 @@ private:
     uint64_t cap_, top_ = 0;
     uint32_t max_batch_;
     bool keep_pinned_;
+    uint32_t id_stride_, id_offset_;
     std::vector<uint8_t> l2_;
     std::vector<uint32_t> slot_;   // (id * 8 + LOD) -> entry index + 1, 0 when absent
     std::vector<uint32_t> stamp_;  // duplicate pairs within one submitted request
@@ -464,6 +472,276 @@ private:
     std::vector<uint64_t> created_, waiters_tmp_;
     uint64_t next_req_ = 0;
     ServeStats st_;
+};
+
+// Brick-sharded serving: the cache is partitioned by brick id.  Brick b
+// belongs to shard b mod T, which knows it as brick b / T; every shard is a
+// Scheduler over its own contiguous range of the cache and its own backend
+// (streams), so T host threads can serve a trace side by side without
+// sharing any scheduling state.  Every request is submitted to every shard
+// with the pairs that shard owns (possibly none), so request ids agree across
+// shards.  A request completes when its last part does: its admission and
+// completion times are the latest over its parts, its pair counts the sums,
+// and it is rejected when a part is.  Admission is in arrival order within a
+// shard; across shards a later request can be admitted by one shard while an
+// earlier one still waits in another.  Shards keep a completed part pinned
+// until the whole request has completed (then until the next step, or with
+// keep_pinned until release).  With T = 1 this is the Scheduler.
+template <class Backend>
+class ShardSet {
+public:
+    // be[w]: backend of shard w, whose batches carry offsets relative to base[w];
+    // cap[w]: elements of shard w's range
+    ShardSet(const std::vector<Backend*>& be, const std::vector<uint64_t>& base, const std::vector<uint64_t>& cap,
+             const uint8_t* brick_log2b, uint32_t n_bricks, uint32_t max_batch, bool keep_pinned)
+        : T_((uint32_t)be.size()), keep_(keep_pinned), base_(base), l2_(brick_log2b, brick_log2b + n_bricks),
+          part_(be.size()) {
+        for (uint32_t w = 0; w < T_; ++w) {
+            const uint32_t nl = n_bricks / T_ + (w < n_bricks % T_ ? 1u : 0u);
+            std::vector<uint8_t> l2(nl);
+            for (uint32_t i = 0; i < nl; ++i) l2[i] = brick_log2b[(uint64_t)i * T_ + w];
+            // several shards: parts stay held until the shard set releases them
+            sh_.emplace_back(
+                new Scheduler<Backend>(*be[w], cap[w], l2.data(), nl, max_batch, keep_pinned || T_ > 1, T_, w));
+        }
+    }
+
+    uint32_t shards() const { return T_; }
+
+    // false when a pair names no brick or a LOD beyond its side
+    bool valid(const uint32_t* ids, const uint8_t* lods, uint64_t n) const {
+        for (uint64_t j = 0; j < n; ++j)
+            if (ids[j] >= l2_.size() || lods[j] > l2_[ids[j]]) return false;
+        return true;
+    }
+
+    bool submit(const uint32_t* ids, const uint8_t* lods, uint32_t n, double t_arrival, uint64_t* req) {
+        if (!valid(ids, lods, n)) return false;
+        if (T_ == 1) return sh_[0]->submit(ids, lods, n, t_arrival, req);
+        for (auto& p : part_) {
+            p.ids.clear();
+            p.lods.clear();
+        }
+        for (uint32_t j = 0; j < n; ++j) {
+            Part& p = part_[ids[j] % T_];
+            p.ids.push_back(ids[j] / T_);
+            p.lods.push_back(lods[j]);
+        }
+        for (uint32_t w = 0; w < T_; ++w)
+            sh_[w]->submit(part_[w].ids.data(), part_[w].lods.data(), (uint32_t)part_[w].ids.size(), t_arrival, req);
+        Acc& a = acc_[*req];
+        a.left = T_;
+        a.d = ServeDone{*req, t_arrival, t_arrival, t_arrival, 0, 0, 0};
+        return true;
+    }
+
+    bool step(double now) {
+        // parts of requests completed (or rejected) since the last step
+        for (uint64_t r : release_next_)
+            for (auto& s : sh_) s->release(r);
+        release_next_.clear();
+        bool busy = false;
+        for (auto& s : sh_) busy |= s->step(now);
+        return busy;
+    }
+
+    std::vector<ServeDone> drain() {
+        if (T_ == 1) return sh_[0]->drain();
+        std::vector<ServeDone> out;
+        for (auto& s : sh_)
+            for (const ServeDone& d : s->drain()) merge(d, out);
+        return out;
+    }
+
+    bool release(uint64_t req) {
+        bool any = false;
+        for (auto& s : sh_) any |= s->release(req);
+        return any;
+    }
+
+    // element offset of a resident pair in the whole cache
+    bool where(uint32_t id, uint8_t lod, uint64_t* off) const {
+        if (id >= l2_.size()) return false;
+        const uint32_t w = id % T_;
+        if (!sh_[w]->where(id / T_, lod, off)) return false;
+        *off += base_[w];
+        return true;
+    }
+
+    ServeStats stats() {
+        ServeStats t;
+        for (auto& s : sh_) {
+            const ServeStats& u = s->stats();
+            t.requests_done += u.requests_done;
+            t.pairs_requested += u.pairs_requested;
+            t.hits += u.hits;
+            t.joined += u.joined;
+            t.decoded += u.decoded;
+            t.evictions += u.evictions;
+            t.resets += u.resets;
+            t.batches += u.batches;
+            t.splits += u.splits;
+            t.decoded_elements += u.decoded_elements;
+            t.requested_elements += u.requested_elements;
+            t.top += u.top;
+            t.resident += u.resident;
+            t.pinned += u.pinned;
+            t.max_batch_seen = std::max(t.max_batch_seen, u.max_batch_seen);
+        }
+        // a request counts once, when all its parts completed without a rejection
+        if (T_ > 1) t.requests_done = done_ok_;
+        return t;
+    }
+
+    // Serve a whole trace, one host thread per shard: request r holds pairs
+    // [starts[r], starts[r + 1]) and arrives at t0 + arrival[r] on clock()
+    // (nondecreasing); out[r] receives its record, times relative to t0.
+    // ok(w) is asked after every step of shard w (a backend error) and stops
+    // the run when false.  Completions of requests submitted before the run
+    // stay queued for drain().  The pairs must be valid.
+    template <class Clock, class Ok>
+    bool run(const uint32_t* ids, const uint8_t* lods, const uint64_t* starts, uint32_t n_req, const double* arrival,
+             double t0, Clock clock, Ok ok, ServeDone* out) {
+        std::vector<std::vector<ServeDone>> parts(T_), early(T_);
+        std::vector<std::vector<uint64_t>> late(T_);  // parts completed in a shard's last step
+        std::atomic<bool> stop{false};
+        auto serve = [&](uint32_t w) {
+            Scheduler<Backend>& s = *sh_[w];
+            // this shard's pairs of every request, as local brick ids
+            std::vector<uint32_t> li;
+            std::vector<uint8_t> ll;
+            std::vector<uint64_t> ls;
+            const uint32_t* pi = ids;
+            const uint8_t* pl = lods;
+            const uint64_t* ps = starts;
+            if (T_ > 1) {
+                ls.assign(n_req + 1, 0);
+                for (uint32_t r = 0; r < n_req; ++r) {
+                    for (uint64_t j = starts[r]; j < starts[r + 1]; ++j)
+                        if (ids[j] % T_ == w) {
+                            li.push_back(ids[j] / T_);
+                            ll.push_back(lods[j]);
+                        }
+                    ls[r + 1] = li.size();
+                }
+                pi = li.data();
+                pl = ll.data();
+                ps = ls.data();
+            }
+            std::vector<ServeDone>& mine = parts[w];
+            mine.resize(n_req);
+            std::vector<uint64_t> rel;  // this shard's parts of this run to release at its next step
+            uint32_t next = 0, done = 0;
+            uint64_t first = 0, rid = 0;
+            while (done < n_req && !stop.load(std::memory_order_relaxed)) {
+                // (the caller reads no cache contents during a run, so without
+                // keep_pinned a part need not wait for its request's other parts)
+                for (uint64_t r : rel) s.release(r);
+                rel.clear();
+                // requests are handed to the scheduler as they arrive
+                const double now = clock();
+                for (; next < n_req && t0 + arrival[next] <= now; ++next) {
+                    s.submit(pi + ps[next], pl + ps[next], (uint32_t)(ps[next + 1] - ps[next]), t0 + arrival[next],
+                             &rid);
+                    if (next == 0) first = rid;
+                }
+                s.step(clock());
+                if (!ok(w)) {
+                    stop.store(true);
+                    break;
+                }
+                for (const ServeDone& d : s.drain()) {
+                    if (next > 0 && d.req >= first && d.req - first < n_req) {
+                        mine[d.req - first] = d;
+                        ++done;
+                        if (T_ > 1 && !keep_) rel.push_back(d.req);
+                    } else {
+                        early[w].push_back(d);  // a request submitted before this run
+                    }
+                }
+                // idle until the next arrival when nothing is waiting, queued or in flight
+                if (s.in_flight() == 0 && next < n_req && s.next_arrival() < 0) {
+                    const double na = t0 + arrival[next], t = clock();
+                    if (na > t + 2e-4) std::this_thread::sleep_for(std::chrono::duration<double>(na - t - 1e-4));
+                }
+            }
+            late[w].swap(rel);
+        };
+        if (T_ == 1) {
+            serve(0);
+        } else {
+            std::vector<std::thread> th;
+            for (uint32_t w = 0; w < T_; ++w) th.emplace_back(serve, w);
+            for (auto& t : th) t.join();
+        }
+        for (auto& l : late) release_next_.insert(release_next_.end(), l.begin(), l.end());
+        if (stop.load()) return false;
+        for (uint32_t r = 0; r < n_req; ++r) {
+            ServeDone d = parts[0][r];
+            for (uint32_t w = 1; w < T_; ++w) fold(d, parts[w][r]);
+            if (T_ > 1 && d.status == 0) ++done_ok_;
+            if (T_ > 1 && keep_ && d.status != 0) release_next_.push_back(d.req);  // parts held by a rejected request
+            d.t_arrival -= t0;
+            d.t_admit -= t0;
+            d.t_done -= t0;
+            out[r] = d;
+        }
+        for (uint32_t w = 0; w < T_; ++w)
+            for (const ServeDone& d : early[w]) {
+                if (T_ == 1) early_done_.push_back(d);
+                else merge(d, early_done_);
+            }
+        return true;
+    }
+
+    // completions of requests submitted before a run, found during it
+    std::vector<ServeDone> take_early() {
+        std::vector<ServeDone> d;
+        d.swap(early_done_);
+        return d;
+    }
+
+private:
+    struct Part {
+        std::vector<uint32_t> ids;
+        std::vector<uint8_t> lods;
+    };
+    struct Acc {
+        uint32_t left = 0;
+        ServeDone d;
+    };
+    // part b of a request folded into its record a
+    static void fold(ServeDone& a, const ServeDone& b) {
+        a.t_admit = std::max(a.t_admit, b.t_admit);
+        a.t_done = std::max(a.t_done, b.t_done);
+        a.n_pairs += b.n_pairs;
+        a.n_decoded += b.n_decoded;
+        a.status = std::min(a.status, b.status);
+    }
+    void merge(const ServeDone& d, std::vector<ServeDone>& out) {
+        auto it = acc_.find(d.req);
+        if (it == acc_.end()) return;
+        fold(it->second.d, d);
+        if (--it->second.left == 0) {
+            const ServeDone& w = it->second.d;
+            out.push_back(w);
+            done_ok_ += w.status == 0 ? 1u : 0u;
+            // unpinned at the next step, unless the caller releases it
+            if (!keep_ || w.status != 0) release_next_.push_back(w.req);
+            acc_.erase(it);
+        }
+    }
+
+    uint32_t T_;
+    bool keep_;
+    std::vector<uint64_t> base_;
+    std::vector<uint8_t> l2_;
+    std::vector<std::unique_ptr<Scheduler<Backend>>> sh_;
+    std::vector<Part> part_;
+    std::unordered_map<uint64_t, Acc> acc_;
+    std::vector<ServeDone> early_done_;
+    std::vector<uint64_t> release_next_;
+    uint64_t done_ok_ = 0;
 };
 
 }  // namespace csgv

@@ -1,8 +1,9 @@
 """Served decode on the GPU: a stream of frustum requests through the server
-(cache, admission, continuous batching on two streams).  Every completed
-request's cache slots must equal (a) the same pairs decoded alone with the
-plain one-launch-per-brick form and (b) the CPU oracle -- the result of a
-request is the same alone and in the mix, bit for bit."""
+(cache, admission, continuous batching on two streams), with the cache whole
+or split into brick shards.  Every completed request's cache slots must equal
+(a) the same pairs decoded alone with the plain one-launch-per-brick form and
+(b) the CPU oracle -- the result of a request is the same alone and in the
+mix, bit for bit."""
 import sys
 
 import numpy as np
@@ -37,18 +38,30 @@ def _alone(P, dv, ids, lods):
     return out.cpu().numpy().view(np.uint32), offs
 
 
-def test_served_requests_equal_alone_and_oracle(P):
+def _cache_for(ids, lods, starts, shards, slack):
+    """Cache elements that hold `slack` times the largest part any shard gets."""
+    el = np.int64(1) << (3 * (5 - lods.astype(np.int64)))
+    part = 0
+    for w in range(shards):
+        m = (ids % shards) == w
+        part = max(part, int(np.add.reduceat(np.where(m, el, 0), starts[:-1].astype(np.int64)).max()))
+    return shards * (int(slack * part) + 64)
+
+
+@pytest.mark.parametrize("shards", [1, 4])
+def test_served_requests_equal_alone_and_oracle(P, shards):
     import torch
     vol = synth.neurite_u32(256, 600, seed=12)
     c = oracle.encode_volume(vol, 5, nthreads=8)
     dv = P.DeviceVolume(c)
     grid = (8, 8, 8)
     ids, lods, starts, arr = workloads.frustum_requests(60, grid, 2000.0, seed=5, n_max=256, orbit=(0.75, 3.0))
-    per = np.add.reduceat(np.int64(1) << (3 * (5 - lods.astype(np.int64))), starts[:-1].astype(np.int64))
-    cache_elems = int(1.1 * per.max())  # well under the volume: eviction and slot reuse across the stream
+    cache_elems = _cache_for(ids, lods, starts, shards, 1.1)  # well under the volume: eviction and slot reuse
     assert cache_elems < 0.6 * 512 * 32 ** 3
     cache = torch.zeros(cache_elems, dtype=torch.int32, device="cuda")
-    srv = P.csgv.csgv_server(dv.info, dv.tensor, cache, cache_elems, n_streams=2, max_batch=512, keep_pinned=True)
+    _say("shards", shards, "cache elements", cache_elems)
+    srv = P.csgv.csgv_server(dv.info, dv.tensor, cache, cache_elems, n_streams=2, max_batch=512, keep_pinned=True,
+                             n_shards=shards)
     t0 = srv.clock()
     for r in range(60):
         a, b = int(starts[r]), int(starts[r + 1])
@@ -80,16 +93,17 @@ def test_served_requests_equal_alone_and_oracle(P):
     srv.destroy()
 
 
-def test_served_trace_run_completes(P):
+@pytest.mark.parametrize("shards", [1, 4])
+def test_served_trace_run_completes(P, shards):
     import torch
     vol = synth.voronoi_voids(256, 2500, seed=6)
     c = oracle.encode_volume(vol, 5, nthreads=8)
     dv = P.DeviceVolume(c)
     ids, lods, starts, arr = workloads.frustum_requests(300, (8, 8, 8), 3000.0, seed=9, n_max=512)
-    per = np.add.reduceat(np.int64(1) << (3 * (5 - lods.astype(np.int64))), starts[:-1].astype(np.int64))
-    cache_elems = int(1.5 * per.max())
+    cache_elems = _cache_for(ids, lods, starts, shards, 1.5)
     cache = torch.zeros(cache_elems, dtype=torch.int32, device="cuda")
-    srv = P.csgv.csgv_server(dv.info, dv.tensor, cache, cache_elems, n_streams=3, max_batch=1024)
+    _say("shards", shards, "cache elements", cache_elems)
+    srv = P.csgv.csgv_server(dv.info, dv.tensor, cache, cache_elems, n_streams=3, max_batch=1024, n_shards=shards)
     rec = srv.run(ids, lods, starts, arr)
     lat = rec["t_done"] - rec["t_arrival"]
     _say("trace: p50 %.3f ms p99 %.3f ms" % (1e3 * np.percentile(lat, 50), 1e3 * np.percentile(lat, 99)))
@@ -98,4 +112,15 @@ def test_served_trace_run_completes(P):
     s = srv.stats()
     assert s["requests_done"] == 300 and s["failed_tasks"] == 0
     assert s["hits"] + s["joined"] + s["decoded"] == s["pairs_requested"]
+    distinct = [len(set(zip(ids[a:b].tolist(), lods[a:b].tolist()))) for a, b in zip(starts[:-1], starts[1:])]
+    assert rec["n_pairs"].tolist() == distinct and int(rec["n_decoded"].sum()) == s["decoded"]
+    # after the run, every pair of the trace's last request is resident where the oracle puts its labels
+    a, b = int(starts[-2]), int(starts[-1])
+    torch.cuda.synchronize()
+    host = cache.cpu().numpy().view(np.uint32)
+    got = np.concatenate([host[srv.where(int(i), int(l)):srv.where(int(i), int(l)) + (32 >> int(l)) ** 3]
+                          for i, l in zip(ids[a:b], lods[a:b])])
+    offs, total = P.dense_offsets(np.full(b - a, 5, np.uint8), lods[a:b])
+    want, wst = oracle.decode_tasks(c, ids[a:b], lods[a:b], offs, total, 4, nthreads=8)
+    assert (wst == 0).all() and np.array_equal(got, want)
     srv.destroy()

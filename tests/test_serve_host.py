@@ -24,13 +24,14 @@ def sim():
     src = os.path.join(HERE, "serve_sim.cpp")
     hdr = os.path.join(HERE, "..", "paper_2609_36898_amd", "csrc", "serve_core.h")
     if not os.path.exists(SO) or os.path.getmtime(SO) < max(os.path.getmtime(src), os.path.getmtime(hdr)):
-        subprocess.run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", src, "-o", SO + ".tmp"], check=True)
+        subprocess.run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread", src, "-o", SO + ".tmp"],
+                       check=True)
         os.replace(SO + ".tmp", SO)
     lib = ctypes.CDLL(SO)
     P = ctypes.c_void_p
     lib.sim_run.argtypes = [P, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32, ctypes.c_int,
-                            ctypes.c_int, P, P, P, ctypes.c_uint32, P, ctypes.c_double, P, P, P, P, P,
-                            ctypes.c_char_p, ctypes.c_int]
+                            ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_uint32, P, ctypes.c_double,
+                            P, P, P, P, P, P, ctypes.c_char_p, ctypes.c_int]
     return lib
 
 
@@ -38,7 +39,8 @@ STATS = ["requests_done", "pairs_requested", "hits", "decoded", "evictions", "re
          "decoded_elements", "requested_elements", "top", "pinned", "max_batch_seen", "joined", "splits"]
 
 
-def run(lib, l2, cache, ids, lods, starts, arrival, streams=2, max_batch=64, keep_pinned=0, delay=3, dt=1e-3):
+def run(lib, l2, cache, ids, lods, starts, arrival, streams=2, max_batch=64, keep_pinned=0, delay=3, dt=1e-3,
+        shards=1, threaded=0, with_pairs=False):
     n_req = len(starts) - 1
     l2 = np.ascontiguousarray(l2, dtype=np.uint8)
     ids = np.ascontiguousarray(ids, dtype=np.uint32)
@@ -49,13 +51,16 @@ def run(lib, l2, cache, ids, lods, starts, arrival, streams=2, max_batch=64, kee
     t_done = np.zeros(n_req)
     status = np.zeros(n_req, dtype=np.int32)
     ndec = np.zeros(n_req, dtype=np.uint32)
+    npairs = np.zeros(n_req, dtype=np.uint32)
     stats = np.zeros(14, dtype=np.uint64)
     err = ctypes.create_string_buffer(512)
-    rc = lib.sim_run(l2.ctypes.data, len(l2), cache, streams, max_batch, keep_pinned, delay, ids.ctypes.data,
-                     lods.ctypes.data, starts.ctypes.data, n_req, arrival.ctypes.data, dt, t_adm.ctypes.data,
-                     t_done.ctypes.data, status.ctypes.data, ndec.ctypes.data, stats.ctypes.data, err, 512)
+    rc = lib.sim_run(l2.ctypes.data, len(l2), cache, streams, max_batch, keep_pinned, delay, shards, threaded,
+                     ids.ctypes.data, lods.ctypes.data, starts.ctypes.data, n_req, arrival.ctypes.data, dt,
+                     t_adm.ctypes.data, t_done.ctypes.data, status.ctypes.data, ndec.ctypes.data, npairs.ctypes.data,
+                     stats.ctypes.data, err, 512)
     assert rc == 0, err.value.decode()
-    return t_adm, t_done, status, ndec, dict(zip(STATS, (int(x) for x in stats)))
+    out = (t_adm, t_done, status, ndec, dict(zip(STATS, (int(x) for x in stats))))
+    return out + (npairs,) if with_pairs else out
 
 
 def _frustum_trace(n, grid, rate, seed):
@@ -186,3 +191,60 @@ def test_eviction_follows_least_recent_use(sim):
     assert (st == 0).all()
     assert list(ndec) == [3, 0, 1, 0, 1]
     assert s["evictions"] == 2 and s["resets"] == 0
+
+
+def _distinct_pairs(ids, lods, starts):
+    return np.array([len(set(zip(ids[a:b].tolist(), lods[a:b].tolist())))
+                     for a, b in zip(starts[:-1].astype(np.int64), starts[1:].astype(np.int64))])
+
+
+def test_sharded_cache_keeps_every_invariant(sim):
+    # brick shards stepped in turn: every pair of a completed request sits in
+    # its shard's range where it was decoded, admission times stay in arrival
+    # order, and a request's pair counts are the sums over its parts
+    grid = (16, 16, 16)
+    ids, lods, starts, arr = _frustum_trace(300, grid, 500.0, seed=4)
+    l2 = np.full(16 ** 3, 5, np.uint8)
+    per_req = np.add.reduceat(np.int64(1) << (3 * (5 - lods.astype(np.int64))), starts[:-1].astype(np.int64))
+    for shards in (2, 3, 8):
+        cache = int(3 * per_req.max())
+        t_adm, t_done, st, ndec, s, npairs = run(sim, l2, cache, ids, lods, starts, arr, shards=shards,
+                                                 with_pairs=True)
+        assert (st == 0).all() and s["requests_done"] == 300
+        assert (t_done >= t_adm).all() and (t_adm >= arr - 1e-12).all()
+        assert np.array_equal(npairs, _distinct_pairs(ids, lods, starts))
+        assert s["hits"] + s["joined"] + s["decoded"] == s["pairs_requested"] == int(npairs.sum())
+        assert int(ndec.sum()) == s["decoded"] and s["evictions"] > 0 and s["pinned"] == 0
+        assert s["top"] <= cache
+
+
+def test_sharded_threads_serve_a_trace(sim):
+    # one host thread per shard on the real clock: every request completes,
+    # each record is its own request's, and the counts add up
+    grid = (16, 16, 16)
+    ids, lods, starts, arr = _frustum_trace(400, grid, 20000.0, seed=6)
+    l2 = np.full(16 ** 3, 5, np.uint8)
+    want = _distinct_pairs(ids, lods, starts)
+    # (with keep_pinned nothing is released during the run: the cache holds the whole trace)
+    for shards, keep, cache in ((1, 0, 1 << 27), (4, 0, 1 << 27), (8, 1, 1 << 31)):
+        t_adm, t_done, st, ndec, s, npairs = run(sim, l2, cache, ids, lods, starts, arr * 0.02, streams=2,
+                                                 max_batch=128, keep_pinned=keep, delay=2, shards=shards,
+                                                 threaded=1, with_pairs=True)
+        assert (st == 0).all() and s["requests_done"] == 400
+        assert np.array_equal(npairs, want)
+        assert (t_done >= t_adm).all() and (t_adm >= arr * 0.02 - 1e-9).all()
+        assert s["hits"] + s["joined"] + s["decoded"] == s["pairs_requested"] == int(want.sum())
+        assert int(ndec.sum()) == s["decoded"] and s["pinned"] == 0
+
+
+def test_sharded_rejection_of_an_oversized_part(sim):
+    # a part larger than its shard's range rejects the whole request; the
+    # others proceed
+    l2 = np.full(64, 5, np.uint8)
+    ids = np.array([0, 0, 2, 4, 6, 8, 1], np.uint32)  # request 1: five bricks of shard 0
+    lods = np.zeros(7, np.uint8)
+    starts = np.array([0, 1, 6, 7], np.uint64)
+    arr = np.array([0.0, 0.001, 0.002])
+    _, _, st, _, s = run(sim, l2, 2 * 4 * 32 ** 3, ids, lods, starts, arr, shards=2)
+    assert list(st) == [0, -1, 0]
+    assert s["requests_done"] == 2
