@@ -39,10 +39,16 @@
 // it by chasing, which terminates because every target precedes its source
 // in Morton order.
 //
-// rANS-coded records are first decoded into 4-bit symbols in the work-group's
-// scratch: every 64-lane group of the interleaved coder is one wavefront, and
-// the lanes that renormalise in a round find their word offsets with a ballot
-// and a masked bit count.
+// rANS-coded records are first decoded into 4-bit symbols (in LDS for a cube
+// of side <= 16 when they fit, else in the work-group's scratch): every 64-lane
+// group of the interleaved coder is one wavefront, and the lanes that
+// renormalise in a round find their word offsets with a ballot and a masked
+// bit count.  The decoding table stays in LDS across tasks until a level-5
+// decode reuses its space.
+//
+// Levels 0..2 (at most 73 nodes) are decoded by wavefront 0 alone, with wave
+// barriers; meanwhile lane 0 of the last wavefront parses the work-group's
+// next task (claimed when the current one started) into a second header.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -74,16 +80,20 @@ struct TaskHdr {
 };
 
 struct Shared {
-    TaskHdr h;
+    TaskHdr h;   // the task being decoded
+    TaskHdr hn;  // the work-group's next task, parsed ahead
     uint32_t err;
+    uint32_t tab_ok;                     // the rANS table is in LDS from an earlier task
+    uint32_t nexp;                       // expanding nodes of the parent level of the next level
+    uint32_t adv;                        // PALETTE_ADV operations decoded so far (handed between phases)
     uint32_t pub[2][kMaxWaves][4];       // per pass and wave: run summary (f, n, a)
-    uint32_t red[kMaxWaves + 2];
     uint32_t E[kEWords];                 // expansion bitmaps of levels 0..4
     uint16_t wpre[kEWords];              // exclusive popcount prefix of each bitmap word
     alignas(16) uint16_t G[kFullSlots];  // full grids of levels 0..4 (fast path)
     alignas(16) uint8_t U[kUBytes];      // parent list of the level being decoded | staged palette
 };
 static_assert(sizeof(Shared) % 16 == 0, "the slot area follows Shared 16-byte aligned");
+static_assert(sizeof(TaskHdr) % 4 == 0 && sizeof(TaskHdr) / 4 <= 128, "a header is copied one word per thread");
 static_assert(offsetof(Shared, U) == offsetof(Shared, G) + sizeof(Shared::G) &&
                   offsetof(Shared, U) + sizeof(Shared::U) == sizeof(Shared),
               "grids, parent list and slot area form one range (rANS staging)");
@@ -111,28 +121,17 @@ __device__ __forceinline__ uint32_t compact3(uint32_t v) {
     return v;
 }
 
-// Exclusive sum over the block; *total = sum.
+// Barrier of the threads that decode a level: the work-group, or (NT = 64)
+// wavefront 0 alone, whose LDS accesses complete in order.
 template <int NT>
-__device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t* total, uint32_t* red) {
-    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
-    uint32_t incl = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t o = __shfl_up(incl, d, 64);
-        if (lane >= (uint32_t)d) incl += o;
+__device__ __forceinline__ void lsync() {
+    if (NT == 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
     }
-    if (lane == 63) red[wave] = incl;
-    __syncthreads();
-    uint32_t base = 0, tot = 0;
-#pragma unroll
-    for (int w = 0; w < NT / 64; ++w) {
-        uint32_t x = red[w];
-        base += (uint32_t)w < wave ? x : 0u;
-        tot += x;
-    }
-    __syncthreads();
-    *total = tot;
-    return base + incl - v;
 }
 
 // 2-state transfer function of one symbol, or of a run of symbols:
@@ -154,6 +153,17 @@ constexpr int kDppWaveShr1 = 0x138;  // lane l takes lane l - 1
 constexpr int kDppBcast15 = 0x142;   // rows 1, 3 take lane 15 of the row before
 constexpr int kDppBcast31 = 0x143;   // rows 2, 3 take lane 31
 constexpr uint32_t kFnId = 2u;       // transfer function that keeps the state
+
+// inclusive sum over the wavefront (lane 0 first)
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
+    x += dpp<kDppRowShr + 1>(0u, x);
+    x += dpp<kDppRowShr + 2>(0u, x);
+    x += dpp<kDppRowShr + 4>(0u, x);
+    x += dpp<kDppRowShr + 8>(0u, x);
+    x += dpp<kDppBcast15, 0xA>(0u, x);
+    x += dpp<kDppBcast31, 0xC>(0u, x);
+    return x;
+}
 
 // -------------------------------------------------------------- palette
 // Palette entry idx: staged in LDS (PAL_LDS) or read from the record.  LT is
@@ -257,6 +267,20 @@ __device__ __forceinline__ void parse_task(const Params& P, uint32_t task, TaskH
 }
 
 
+// The work-group's next task: claimed by lane 0 of its last wavefront (jt, in
+// that lane's register) when a task starts, and parsed into sh.hn by the same
+// lane while that wavefront has nothing else to do (levels 0..2 are decoded by
+// wavefront 0 alone), else at the end of the task.
+struct Ahead {
+    uint32_t jt;
+    bool done;
+};
+
+__device__ __forceinline__ void parse_ahead(const Params& P, TaskHdr& hn, uint32_t jt) {
+    if (jt < P.n_tasks) parse_task(P, P.order ? P.order[jt] : jt, hn);
+    else hn.task = 0xFFFFFFFFu;
+}
+
 // ----------------------------------------------------------------- rANS
 // Decode the first h.nsym symbols of the record into 4-bit symbols at nib[]
 // (low nibble first).  Wavefront w handles lane groups w, w + NW, ...  A
@@ -327,29 +351,30 @@ __device__ __forceinline__ void rans_decode(const Params& P, Shared& sh, const u
     }
 }
 
-// The same decode with the record's words and the decoded symbols staged in
-// LDS (`stage`, the level grids and slot area, idle until the levels start):
-// a lane that renormalises reads its word from LDS, and the symbols reach the
-// work-group's scratch in one coalesced copy at the end, so no round waits on
-// a global store.  The caller checks that words and symbols fit.
+// The same decode with the record's words staged in LDS (`stage`, the level
+// grids and slot area, idle until the levels start) and the symbols written
+// to LDS at `nl`: a lane that renormalises reads its word from LDS, and no
+// round waits on a global store.  With `nib` set, the symbols then reach it
+// in one coalesced copy.  The caller checks that words and symbols fit.
 template <int NT>
 __device__ __forceinline__ void rans_decode_lds(const Params& P, Shared& sh, const uint32_t* tab, uint8_t* stage,
-                                                uint8_t* nib) {
+                                                uint8_t* nl, uint8_t* nib) {
     const TaskHdr& h = sh.h;
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const uint32_t W = 1u << h.log2W, G = (W + 63) / 64, lanes = W < 64 ? W : 64;
     const uint32_t nsym = h.nsym, tw = h.gstart[G - 1] + h.gw[G - 1];
     uint16_t* const wl = (uint16_t*)stage;
-    uint8_t* const nl = stage + ((2u * tw + 15u) & ~15u);
     const uint16_t* const wg = (const uint16_t*)(P.vol + h.pay_off);
+    const uint32_t* states = (const uint32_t*)(P.vol + h.states_off);
+    // the state of this wave's first lane group is loaded along with the words
+    uint32_t x0 = wave < G && lane < lanes ? states[64 * wave + lane] : 0u;
     for (uint32_t q = tid; q < tw / 2u; q += NT) ((uint32_t*)wl)[q] = ((const uint32_t*)wg)[q];
     if ((tw & 1u) && tid == 0) wl[tw - 1u] = wg[tw - 1u];
     __syncthreads();
-    const uint32_t* states = (const uint32_t*)(P.vol + h.states_off);
     for (uint32_t g = wave; g < G; g += NT / 64) {
         const bool active = lane < lanes;
         const uint32_t gcount = h.gw[g], gbase = h.gstart[g];
-        uint32_t x = active ? states[64 * g + lane] : 0u;
+        uint32_t x = g == wave ? x0 : active ? states[64 * g + lane] : 0u;
         uint32_t gpos = 0, pend = 0;
         bool bad = false;
         __builtin_amdgcn_s_waitcnt(0);
@@ -385,9 +410,11 @@ __device__ __forceinline__ void rans_decode_lds(const Params& P, Shared& sh, con
         }
         if (__ballot(bad) && lane == 0) atomicOr(&sh.err, 1u);
     }
-    __syncthreads();
-    const uint32_t nw = ((nsym + 1u) / 2u + 3u) / 4u;
-    for (uint32_t q = tid; q < nw; q += NT) ((uint32_t*)nib)[q] = ((const uint32_t*)nl)[q];
+    if (nib) {
+        __syncthreads();
+        const uint32_t nw = ((nsym + 1u) / 2u + 3u) / 4u;
+        for (uint32_t q = tid; q < nw; q += NT) ((uint32_t*)nib)[q] = ((const uint32_t*)nl)[q];
+    }
 }
 
 // ------------------------------------------------------------ level store
@@ -442,27 +469,40 @@ __device__ __forceinline__ uint32_t vox6(uint32_t p) {
 }
 
 // ------------------------------------------------------------ level set-up
-// Expanding parents of level i-1 (i >= 1): exclusive popcount prefix of their
-// bitmap words, the list of their node indices by rank, and (full level i)
-// the children's initial slots.  Returns the number of expanding parents.
-template <int NT, typename V, bool BIG, bool LIST_LDS, bool PL5>
-__device__ __forceinline__ uint32_t level_setup(Shared& sh, const Store<V>& st, uint32_t i, uint32_t t) {
-    const uint32_t tid = threadIdx.x;
-    const uint32_t pl = i - 1, pn = 1u << (3 * pl), pw = ewords(pl);
-    // parents' bitmap: levels 0..4 in LDS, level 5 in scratch
-    uint32_t* const Ep = PL5 ? st.E5 : st.E + ebase(pl);
+// Expanding parents of level i (the nodes of level pl = i - 1 whose bit is set
+// in its bitmap), in two steps.  level_prefix (wavefront 0): exclusive
+// popcount prefix of the bitmap's words, each lane summing a run of
+// consecutive words, and the number of expanding parents in sh.nexp.
+// level_fill (all threads of the level): the list of their node indices by
+// rank and, for a full level i, the children's initial slots; the bitmap of
+// level i is cleared when level i has children.
+template <typename V, bool PL5>
+__device__ __forceinline__ void level_prefix(Shared& sh, const Store<V>& st, uint32_t pl) {
+    const uint32_t lane = lane_id(), pn = 1u << (3 * pl), pw = ewords(pl);
+    const uint32_t mask = pn < 32 ? (1u << pn) - 1u : 0xFFFFFFFFu;
+    const uint32_t* const Ep = PL5 ? st.E5 : st.E + ebase(pl);
     uint16_t* const Wp = PL5 ? st.wpre5 : st.wpre + ebase(pl);
-    uint32_t base = 0;
-    for (uint32_t w0 = 0; w0 < pw; w0 += NT) {
-        const uint32_t w = w0 + tid;
-        uint32_t bits = w < pw ? Ep[w] : 0u;
-        if (pn < 32) bits &= (1u << pn) - 1u;
-        uint32_t tot;
-        const uint32_t pre = block_excl_sum<NT>((uint32_t)__popc(bits), &tot, sh.red);
-        if (w < pw) Wp[w] = (uint16_t)(base + pre);
-        base += tot;
-    }
-    __syncthreads();
+    const uint32_t per = (pw + 63u) / 64u, w0 = lane * per;
+    uint32_t sum = 0;
+    for (uint32_t q = 0; q < per; ++q)
+        if (w0 + q < pw) sum += (uint32_t)__popc(Ep[w0 + q] & mask);
+    const uint32_t incl = wave_incl_sum(sum);
+    uint32_t run = incl - sum;
+    for (uint32_t q = 0; q < per; ++q)
+        if (w0 + q < pw) {
+            Wp[w0 + q] = (uint16_t)run;
+            run += (uint32_t)__popc(Ep[w0 + q] & mask);
+        }
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    if (lane == 0) sh.nexp = total;
+}
+
+template <int NT, typename V, bool BIG, bool LIST_LDS, bool PL5>
+__device__ __forceinline__ void level_fill(Shared& sh, const Store<V>& st, uint32_t i, uint32_t t) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t pl = i - 1, pn = 1u << (3 * pl);
+    const uint32_t* const Ep = PL5 ? st.E5 : st.E + ebase(pl);
+    const uint16_t* const Wp = PL5 ? st.wpre5 : st.wpre + ebase(pl);
     constexpr V NOTYET = Slot<V>::kNotYet;
     for (uint32_t q = tid; q < pn; q += NT) {
         const uint32_t bits = Ep[q >> 5] & (pn < 32 ? (1u << pn) - 1u : 0xFFFFFFFFu);
@@ -490,8 +530,7 @@ __device__ __forceinline__ uint32_t level_setup(Shared& sh, const Store<V>& st, 
             for (uint32_t w = tid; w < ewords(5); w += NT) st.E5[w] = 0;
         }
     }
-    __syncthreads();
-    return base;
+    lsync<NT>();
 }
 
 // ------------------------------------------------------------ level passes
@@ -626,28 +665,36 @@ __device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const 
             incl = wave_scan_run(x);
             excl = dpp_run<kDppWaveShr1>(incl);
         }
-        if (lane == 63) {
-            uint32_t* pub = sh.pub[pb][wave];
-            pub[0] = incl.f;
-            pub[1] = incl.n;
-            pub[2] = incl.a;
+        // this wave's entry state, operation base and ADV base (wf, wn, wa), and the
+        // pass totals (tf, tn, ta): one wavefront has them from its own scan
+        uint32_t wf = kFnId, wn = 0, wa = 0, tf, tn, ta;
+        if (NW == 1) {
+            tf = (uint32_t)__builtin_amdgcn_readlane((int)incl.f, 63);
+            tn = (uint32_t)__builtin_amdgcn_readlane((int)incl.n, 63);
+            ta = (uint32_t)__builtin_amdgcn_readlane((int)incl.a, 63);
+        } else {
+            if (lane == 63) {
+                uint32_t* pub = sh.pub[pb][wave];
+                pub[0] = incl.f;
+                pub[1] = incl.n;
+                pub[2] = incl.a;
+            }
+            lsync<NT>();
+            // the waves' totals, scanned over the first NW lanes (one row of 16)
+            RunSum wt{kFnId, 0u, 0u};
+            if (lane < NW) wt = RunSum{sh.pub[pb][lane][0], sh.pub[pb][lane][1], sh.pub[pb][lane][2]};
+            wt = run_then(dpp_run<kDppRowShr + 1>(wt), wt);
+            wt = run_then(dpp_run<kDppRowShr + 2>(wt), wt);
+            wt = run_then(dpp_run<kDppRowShr + 4>(wt), wt);
+            wt = run_then(dpp_run<kDppRowShr + 8>(wt), wt);
+            const RunSum we = dpp_run<kDppRowShr + 1>(wt);
+            wf = (uint32_t)__builtin_amdgcn_readlane((int)we.f, (int)wave);
+            wn = (uint32_t)__builtin_amdgcn_readlane((int)we.n, (int)wave);
+            wa = (uint32_t)__builtin_amdgcn_readlane((int)we.a, (int)wave);
+            tf = (uint32_t)__builtin_amdgcn_readlane((int)wt.f, (int)(NW - 1));
+            tn = (uint32_t)__builtin_amdgcn_readlane((int)wt.n, (int)(NW - 1));
+            ta = (uint32_t)__builtin_amdgcn_readlane((int)wt.a, (int)(NW - 1));
         }
-        __syncthreads();
-        // the waves' totals, scanned over the first NW lanes (one row of 16):
-        // this wave's entry state, operation base and ADV base, and the pass totals
-        RunSum wt{kFnId, 0u, 0u};
-        if (lane < NW) wt = RunSum{sh.pub[pb][lane][0], sh.pub[pb][lane][1], sh.pub[pb][lane][2]};
-        wt = run_then(dpp_run<kDppRowShr + 1>(wt), wt);
-        wt = run_then(dpp_run<kDppRowShr + 2>(wt), wt);
-        wt = run_then(dpp_run<kDppRowShr + 4>(wt), wt);
-        wt = run_then(dpp_run<kDppRowShr + 8>(wt), wt);
-        const RunSum we = dpp_run<kDppRowShr + 1>(wt);
-        const uint32_t wf = (uint32_t)__builtin_amdgcn_readlane((int)we.f, (int)wave);
-        const uint32_t wn = (uint32_t)__builtin_amdgcn_readlane((int)we.n, (int)wave);
-        const uint32_t wa = (uint32_t)__builtin_amdgcn_readlane((int)we.a, (int)wave);
-        const uint32_t tf = (uint32_t)__builtin_amdgcn_readlane((int)wt.f, (int)(NW - 1));
-        const uint32_t tn = (uint32_t)__builtin_amdgcn_readlane((int)wt.n, (int)(NW - 1));
-        const uint32_t ta = (uint32_t)__builtin_amdgcn_readlane((int)wt.a, (int)(NW - 1));
         const uint32_t my_e = (wf >> carry) & 1u;
         const uint32_t my_kb = k_done + ((wn >> (16 * carry)) & kHalf);
         const uint32_t my_ab = adv_done + ((wa >> (16 * carry)) & kHalf);
@@ -779,7 +826,7 @@ __device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const 
                 }
             }
         }
-        __syncthreads();
+        lsync<NT>();
         // references within the pass: chase to a final value (targets precede
         // their sources, so every chain ends within the pass's operations)
         for (uint32_t m = refm; m; m &= m - 1u) {
@@ -805,23 +852,54 @@ __device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const 
 }
 
 // Decode levels 0..t; on return all slots of level t are final unless sh.err.
+// Levels 0..2 (at most 73 nodes) are decoded by wavefront 0 alone, with wave
+// barriers; the other wavefronts wait at the work-group barrier that follows.
+// From level 3 on, all threads decode; wavefront 0 computes the next level's
+// parent prefix after a level's last pass, before the barrier that ends it.
 template <int NT, typename V, bool BIG, bool LIST_LDS>
-__device__ __forceinline__ void decode_levels(const Params& P, Shared& sh, const Store<V>& st, const uint8_t* nib) {
-    const uint32_t t = sh.h.t;
+__device__ __forceinline__ void decode_levels(const Params& P, Shared& sh, const Store<V>& st, const uint8_t* nib,
+                                              Ahead& ah) {
+    const uint32_t t = sh.h.t, wave = threadIdx.x >> 6;
+    const uint32_t tw = t < 2u ? t : 2u;  // last level of wavefront 0 alone
     uint32_t adv_done = 0, pbuf = 0;
-    for (uint32_t i = 0; i <= t; ++i) {
-        uint32_t expected = 1;
-        if (i == 0) {
-            if (t > 0 && threadIdx.x == 0) st.E[ebase(0)] = 0;
-            __syncthreads();
-        } else if (i <= 5) {
-            expected = 8 * level_setup<NT, V, BIG, LIST_LDS, false>(sh, st, i, t);
-        } else {
-            expected = 8 * level_setup<NT, V, BIG, false, true>(sh, st, i, t);
+    if (wave == 0) {
+        for (uint32_t i = 0; i <= tw; ++i) {
+            uint32_t expected = 1;
+            if (i == 0) {
+                if (t > 0 && threadIdx.x == 0) st.E[ebase(0)] = 0;
+                lsync<64>();
+            } else {
+                level_prefix<V, false>(sh, st, i - 1);
+                lsync<64>();
+                expected = 8 * sh.nexp;
+                level_fill<64, V, BIG, LIST_LDS, false>(sh, st, i, t);
+            }
+            level_passes<64, 0, V, BIG, LIST_LDS>(P, sh, st, nib, i, expected, adv_done, pbuf);
+            lsync<64>();
+            if (sh.err) break;
         }
+        if (!sh.err && t > tw) level_prefix<V, false>(sh, st, tw);
+        if (threadIdx.x == 0) sh.adv = adv_done;
+    } else if (threadIdx.x == NT - 64 && !ah.done) {
+        parse_ahead(P, sh.hn, ah.jt);
+        ah.done = true;
+    }
+    __syncthreads();
+    if (sh.err) return;
+    adv_done = sh.adv;
+    pbuf = 0;
+    for (uint32_t i = tw + 1; i <= t; ++i) {
+        const uint32_t expected = 8 * sh.nexp;
+        if (i <= 5) level_fill<NT, V, BIG, LIST_LDS, false>(sh, st, i, t);
+        else level_fill<NT, V, BIG, false, true>(sh, st, i, t);
         if (i <= 4) level_passes<NT, 0, V, BIG, LIST_LDS>(P, sh, st, nib, i, expected, adv_done, pbuf);
         else if (i == 5) level_passes<NT, 1, V, BIG, LIST_LDS>(P, sh, st, nib, i, expected, adv_done, pbuf);
         else level_passes<NT, 2, V, BIG, false>(P, sh, st, nib, i, expected, adv_done, pbuf);
+        // the level's bitmap is final after its last pass: the next level's parent prefix
+        if (i < t && wave == 0) {
+            if (i == 5) level_prefix<V, true>(sh, st, i);
+            else level_prefix<V, false>(sh, st, i);
+        }
         __syncthreads();
         if (sh.err) return;
     }
@@ -981,17 +1059,18 @@ __device__ __forceinline__ void write_output(const Params& P, Shared& sh, const 
     if (P.pal_bits) {
         write_indices<NT, V>(P, sh, st);
     } else if (P.label_bytes == 4) {
-        if (sh.h.pal_lds) write_labels<NT, V, uint32_t, true>(P, sh, st);
+        if (sh.h.pal_lds && sh.h.t > 3) write_labels<NT, V, uint32_t, true>(P, sh, st);
         else write_labels<NT, V, uint32_t, false>(P, sh, st);
     } else {
-        if (sh.h.pal_lds) write_labels<NT, V, uint64_t, true>(P, sh, st);
+        if (sh.h.pal_lds && sh.h.t > 3) write_labels<NT, V, uint64_t, true>(P, sh, st);
         else write_labels<NT, V, uint64_t, false>(P, sh, st);
     }
 }
 
 // ------------------------------------------------------------------ a task
 template <int NT, typename V, bool BIG>
-__device__ __forceinline__ void run_levels(const Params& P, Shared& sh, uint16_t* slots_lds, uint8_t* scratch, const uint8_t* nib) {
+__device__ __forceinline__ void run_levels(const Params& P, Shared& sh, uint16_t* slots_lds, uint8_t* scratch, const uint8_t* nib,
+                                           Ahead& ah) {
     const TaskHdr& h = sh.h;
     Store<V> st;
     st.E = sh.E;
@@ -1010,11 +1089,12 @@ __device__ __forceinline__ void run_levels(const Params& P, Shared& sh, uint16_t
         st.full = (V*)sh.G;
         st.c5 = (V*)slots_lds;
     }
-    if (!BIG && h.t <= 5) decode_levels<NT, V, BIG, true>(P, sh, st, nib);
-    else decode_levels<NT, V, BIG, false>(P, sh, st, nib);
+    if (!BIG && h.t <= 5) decode_levels<NT, V, BIG, true>(P, sh, st, nib, ah);
+    else decode_levels<NT, V, BIG, false>(P, sh, st, nib, ah);
     if (sh.err) return;
-    // palette staging for the output pass (the parent list is no longer needed)
-    if (h.pal_lds && !P.pal_bits) {
+    // palette staging for the output pass (the parent list is no longer needed);
+    // a cube of side <= 8 reads its few labels straight from the record
+    if (h.pal_lds && !P.pal_bits && h.t > 3) {
         const uint32_t words = (h.pc * P.label_bytes + 3) / 4;
         const uint32_t* src = (const uint32_t*)(P.vol + h.pal_off);
         for (uint32_t w = threadIdx.x; w < words; w += NT) ((uint32_t*)sh.U)[w] = src[w];
@@ -1024,15 +1104,21 @@ __device__ __forceinline__ void run_levels(const Params& P, Shared& sh, uint16_t
 }
 
 template <int NT>
-__device__ __forceinline__ void decode_task(const Params& P, Shared& sh, uint16_t* slots_lds, uint8_t* scratch) {
+__device__ __forceinline__ void decode_task(const Params& P, Shared& sh, uint16_t* slots_lds, uint8_t* scratch,
+                                            Ahead& ah) {
     const TaskHdr& h = sh.h;
     if (h.status != kTaskOk) {
         if (h.status == kTaskCorrupt && h.write_ok) zero_output<NT>(P, h);
         return;
     }
-    // the symbols (4 bits each) go to the work-group's scratch, where the level
-    // passes read them as aligned 32-bit words
-    uint8_t* const nib = scratch + kScrSym;
+    // The symbols (4 bits each) are read by the level passes as aligned 32-bit
+    // words: from the work-group's scratch, or for a cube of side <= 16 (levels
+    // 0..4, whose parent lists take at most 1 KiB) from the rest of the parent
+    // list area when they fit there.
+    constexpr uint32_t kListMax4 = 1024;
+    const bool sym_lds = h.t <= 4 && (h.nsym + 1u) / 2u + 4u <= kUBytes - kListMax4;
+    uint8_t* const nib = sym_lds ? sh.U + kListMax4 : scratch + kScrSym;
+    bool tab_used = false;
     if (h.coder == kRaw4) {
         const uint32_t bytes = (h.nsym + 1u) / 2u, words = bytes / 4u;
         const uint32_t* src = (const uint32_t*)(P.vol + h.pay_off);
@@ -1040,30 +1126,43 @@ __device__ __forceinline__ void decode_task(const Params& P, Shared& sh, uint16_
         for (uint32_t b = 4u * words + threadIdx.x; b < bytes; b += NT) nib[b] = P.vol[h.pay_off + b];
         __syncthreads();
     } else {
-        // the rANS table borrows the last 16 KiB of the slot area until the levels
-        // start; the grids, parent list and the rest of the slot area before it can
-        // stage the record's words and the decoded symbols
+        // the rANS table sits in the last 16 KiB of the slot area until level 5
+        // of a fast-path task overwrites it (later tasks find it there until
+        // then); the grids, parent list and the rest of the slot area before it
+        // can stage the record's words and the decoded symbols
         uint8_t* const stage = (uint8_t*)sh.G;
         const uint32_t stage_bytes = (uint32_t)(sizeof(sh.G) + sizeof(sh.U)) + 2u * P.cap16 - 4u * kRansM;
         uint32_t* tab = (uint32_t*)(stage + stage_bytes);
-        const uint4* src = (const uint4*)P.rans_tab;
-        for (uint32_t w = threadIdx.x; w < kRansM / 4; w += NT) ((uint4*)tab)[w] = src[w];
-        __syncthreads();
+        tab_used = true;
+        if (!sh.tab_ok) {
+            const uint4* src = (const uint4*)P.rans_tab;
+            for (uint32_t w = threadIdx.x; w < kRansM / 4; w += NT) ((uint4*)tab)[w] = src[w];
+            __syncthreads();
+        }
         const uint32_t G = ((1u << h.log2W) + 63u) / 64u, tw = h.gstart[G - 1] + h.gw[G - 1];
-        const uint32_t need = ((2u * tw + 15u) & ~15u) + ((h.nsym + 1u) / 2u + 3u) / 4u * 4u;
-        if (need <= stage_bytes) rans_decode_lds<NT>(P, sh, tab, stage, nib);
+        const uint32_t words_bytes = (2u * tw + 15u) & ~15u;
+        const uint32_t sym_bytes = ((h.nsym + 1u) / 2u + 3u) / 4u * 4u;
+        // symbols bound for the parent list area: the staged words must end before it
+        const uint32_t nl_at = (uint32_t)(offsetof(Shared, U) - offsetof(Shared, G)) + kListMax4;
+        if (sym_lds && words_bytes <= nl_at) rans_decode_lds<NT>(P, sh, tab, stage, nib, nullptr);
+        else if (!sym_lds && words_bytes + sym_bytes <= stage_bytes)
+            rans_decode_lds<NT>(P, sh, tab, stage, stage + words_bytes, nib);
         else rans_decode<NT>(P, sh, tab, nib);
         __syncthreads();
     }
+    // level 5 of a fast-path task overwrites the table
+    const bool tab_lost = !h.big && h.t >= 5;
     if (!sh.err) {
-        if (h.big) run_levels<NT, uint32_t, true>(P, sh, slots_lds, scratch, nib);
-        else run_levels<NT, uint16_t, false>(P, sh, slots_lds, scratch, nib);
+        if (h.big) run_levels<NT, uint32_t, true>(P, sh, slots_lds, scratch, nib, ah);
+        else run_levels<NT, uint16_t, false>(P, sh, slots_lds, scratch, nib, ah);
     }
     __syncthreads();
     if (sh.err) {
         if (threadIdx.x == 0) sh.h.status = kTaskCorrupt;
         zero_output<NT>(P, h);
     }
+    // (read again only after the task loop's next barriers)
+    if (threadIdx.x == 0) sh.tab_ok = tab_lost ? 0u : tab_used ? 1u : sh.tab_ok;
 }
 
 // at least 4 waves per SIMD: 128 VGPRs per lane at most
@@ -1074,24 +1173,34 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) de
     uint16_t* slots_lds = reinterpret_cast<uint16_t*>(dyn_smem + sizeof(Shared));
     const uint32_t tid = threadIdx.x;
     uint8_t* scratch = P.scratch + (uint64_t)blockIdx.x * P.scratch_stride;
-    // thread 0 claims a work-group's next task while the current one is decoded:
-    // the atomic's latency hides behind the decode
-    uint32_t jt = 0;
-    if (tid == 0) jt = P.queue ? atomicAdd(P.queue, 1u) : P.task0 + blockIdx.x;
+    // lane 0 of the last wavefront claims and parses the next task while the
+    // current one is decoded (the atomic's and the header loads' latency hide
+    // behind the decode)
+    constexpr uint32_t PT = NT - 64;
+    Ahead ah{0u, true};
+    if (tid == PT) {
+        const uint32_t j0 = P.queue ? atomicAdd(P.queue, 1u) : P.task0 + blockIdx.x;
+        parse_ahead(P, sh.hn, j0);
+        ah.jt = j0 < P.n_tasks ? j0 : P.n_tasks;
+    }
+    if (tid == 0) sh.tab_ok = 0;
     for (;;) {
-        if (tid == 0) {
-            sh.err = 0;
-            if (jt < P.n_tasks) parse_task(P, P.order ? P.order[jt] : jt, sh.h);
-            else sh.h.task = 0xFFFFFFFFu;
-        }
+        __syncthreads();  // sh.hn is parsed, the last task's status written
+        if (tid < sizeof(TaskHdr) / 4) ((uint32_t*)&sh.h)[tid] = ((const uint32_t*)&sh.hn)[tid];
+        if (tid == 0) sh.err = 0;
         __syncthreads();
-        if (tid == 0) jt = P.queue && jt < P.n_tasks ? atomicAdd(P.queue, 1u) : P.n_tasks;
         const uint32_t task = sh.h.task;
         if (task == 0xFFFFFFFFu) break;
-        decode_task<NT>(P, sh, slots_lds, scratch);
-        __syncthreads();
+        if (tid == PT) {
+            ah.jt = P.queue && ah.jt < P.n_tasks ? atomicAdd(P.queue, 1u) : P.n_tasks;
+            ah.done = false;
+        }
+        decode_task<NT>(P, sh, slots_lds, scratch, ah);
+        if (tid == PT && !ah.done) {
+            parse_ahead(P, sh.hn, ah.jt);
+            ah.done = true;
+        }
         if (tid == 0 && P.status) P.status[task] = sh.h.status;
-        __syncthreads();
     }
 }
 
