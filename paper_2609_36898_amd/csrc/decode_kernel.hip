@@ -137,8 +137,19 @@ __device__ __forceinline__ void lsync() {
 // 2-state transfer function of one symbol, or of a run of symbols:
 // bit e = state after the run when it was entered in state e
 // (state 0: the next symbol is an operation; state 1: it is a delta entry).
+__host__ __device__ constexpr uint32_t fn_then_ref(uint32_t first, uint32_t second) {
+    return ((second >> (first & 1)) & 1) | (((second >> ((first >> 1) & 1)) & 1) << 1);
+}
+// all 16 compositions, 2 bits each at bit 2 * (4 * first + second)
+__host__ __device__ constexpr uint32_t fn_then_table() {
+    uint32_t t = 0;
+    for (uint32_t a = 0; a < 4; ++a)
+        for (uint32_t b = 0; b < 4; ++b) t |= fn_then_ref(a, b) << (2 * (4 * a + b));
+    return t;
+}
+constexpr uint32_t kFnThen = fn_then_table();
 __device__ __forceinline__ uint32_t fn_then(uint32_t first, uint32_t second) {
-    return ((second >> (first & 1u)) & 1u) | (((second >> ((first >> 1) & 1u)) & 1u) << 1);
+    return (kFnThen >> (2u * (4u * first + second))) & 3u;
 }
 
 // DPP moves (GFX9 controls).  A lane whose source lane does not exist, or
@@ -376,24 +387,23 @@ __device__ __forceinline__ void rans_decode_lds(const Params& P, Shared& sh, con
         const uint32_t gcount = h.gw[g], gbase = h.gstart[g];
         uint32_t x = g == wave ? x0 : active ? states[64 * g + lane] : 0u;
         uint32_t gpos = 0, pend = 0;
+        const uint32_t gcm1 = gcount ? gcount - 1u : 0u;  // word reads stay inside the group
         bool bad = false;
         __builtin_amdgcn_s_waitcnt(0);
+        // a round without branches: every lane looks its state up and reads a
+        // word; a lane past the symbols keeps its state
         for (uint32_t r0 = 64 * g; r0 < nsym; r0 += W) {
             const uint32_t j = r0 + lane;
             const bool act = active && j < nsym;
-            uint32_t s = 0;
-            if (act) {
-                const uint32_t e = tab[x & (kRansM - 1)];
-                s = e & 15u;
-                x = ((e >> 4) & 0x1FFFu) * (x >> kRansBits) + (e >> 17);
-            }
-            const bool need = act && x < kRansL;
+            const uint32_t e = tab[x & (kRansM - 1)];
+            const uint32_t s = e & 15u;
+            const uint32_t xd = ((e >> 4) & 0x1FFFu) * (x >> kRansBits) + (e >> 17);
+            const bool need = act && xd < kRansL;
             const uint64_t m = __ballot(need);
-            if (need) {
-                const uint32_t widx = gpos + mbcnt(m);
-                if (widx >= gcount) bad = true;
-                else x = (x << 16) | wl[gbase + widx];
-            }
+            const uint32_t widx = gpos + mbcnt(m);
+            const uint32_t wv = wl[gbase + min(widx, gcm1)];
+            bad = bad || (need && widx >= gcount);
+            x = need ? ((xd << 16) | wv) : act ? xd : x;
             gpos += (uint32_t)__popcll(m);
             // two consecutive symbols per byte
             if (W >= 2) {
@@ -535,27 +545,32 @@ __device__ __forceinline__ void level_fill(Shared& sh, const Store<V>& st, uint3
 
 // ------------------------------------------------------------ level passes
 // 2-state automaton summary of a run of symbols for both entry states: f (bit
-// e = exit state when entered in state e), and per entry state the number of
-// operations (n) and of PALETTE_ADV operations (a), entry 0 in the low half,
-// entry 1 in the high half.
+// e = exit state when entered in state e), and per entry state e the number of
+// operations | the number of PALETTE_ADV operations << 16 (p0, p1).  A pass
+// holds at most 8 symbols per thread, so both counts stay below 2^16.
 struct RunSum {
-    uint32_t f, n, a;
+    uint32_t f, p0, p1;
 };
 constexpr uint32_t kHalf = 0xFFFFu;
 
-// the run `b` after the run `a`
+// the run `y` after the run `x`
 __device__ __forceinline__ RunSum run_then(const RunSum& x, const RunSum& y) {
-    const uint32_t s0 = 16u * (x.f & 1u), s1 = 16u * ((x.f >> 1) & 1u);
     RunSum r;
     r.f = fn_then(x.f, y.f);
-    r.n = x.n + ((y.n >> s0) & kHalf) + (((y.n >> s1) & kHalf) << 16);
-    r.a = x.a + ((y.a >> s0) & kHalf) + (((y.a >> s1) & kHalf) << 16);
+    r.p0 = x.p0 + ((x.f & 1u) ? y.p1 : y.p0);
+    r.p1 = x.p1 + ((x.f & 2u) ? y.p1 : y.p0);
     return r;
 }
 
 template <int CTRL, int ROWS = 0xF>
 __device__ __forceinline__ RunSum dpp_run(const RunSum& x) {
-    return RunSum{dpp<CTRL, ROWS>(kFnId, x.f), dpp<CTRL, ROWS>(0u, x.n), dpp<CTRL, ROWS>(0u, x.a)};
+    return RunSum{dpp<CTRL, ROWS>(kFnId, x.f), dpp<CTRL, ROWS>(0u, x.p0), dpp<CTRL, ROWS>(0u, x.p1)};
+}
+
+// bit 4q set where nibble q of lo3 (nibbles of 3 bits) equals c (c given in every nibble)
+__device__ __forceinline__ uint32_t nib_eq(uint32_t lo3, uint32_t c) {
+    const uint32_t t = lo3 ^ c;
+    return ~(t | (t >> 1) | (t >> 2)) & 0x11111111u;
 }
 
 // inclusive scan of run summaries over the wavefront (lane 0 first)
@@ -636,48 +651,53 @@ __device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const 
             nlo = nib32[min(w, w_last)];
             nhi = nib32[min(w + 1u, w_last)];
         }
-        // symbols of this group that belong to the level
-        uint32_t vm = 0;
+        // Masks over the thread's symbols, bit 4q for symbol j0 + q ("nibble
+        // masks"): V4 the symbols of this group that belong to the level
+        uint32_t V4 = 0;
         if (g <= g_last) {
             const uint32_t lo = s0 > j0 ? s0 - j0 : 0u, hi = min(s1 - j0, 1u << lr);
-            vm = ((1u << hi) - 1u) & ~((1u << lo) - 1u);
+            V4 = (hi >= 8u ? 0xFFFFFFFFu : (1u << (4u * hi)) - 1u) & ~((1u << (4u * lo)) - 1u) & 0x11111111u;
         }
+        const uint32_t lo3 = word & 0x77777777u, C4 = (word >> 3) & 0x11111111u;
+        // the automaton state before each symbol for entry state 0 (S0) and 1 (S1):
+        // state 1 = inside a delta chain (the symbol is a delta entry)
+        uint32_t S0 = 0, S1 = 0;
         // a wave holding no symbol of the level skips its summary, scan and decode
         // (it still takes part in the barriers and the waves' scan)
         const bool wave_on = g_first + pg + 64u * wave <= g_last;
         RunSum incl{kFnId, 0u, 0u}, excl{kFnId, 0u, 0u};
         if (wave_on) {
-            RunSum x;
-            uint32_t e0 = 0, e1 = 1, n0 = 0, n1 = 0, a0 = 0, a1 = 0;
+            // a symbol outside the level keeps the state: DELTA code off, continuation on
+            const uint32_t Dv = nib_eq(lo3, 0x66666666u) & V4, Cv = C4 | (~V4 & 0x11111111u);
+            uint32_t e0 = 0, e1 = 1;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const uint32_t sym = (word >> (4 * q)) & 15u, vq = (vm >> q) & 1u;
-                const uint32_t isd = (sym & 7u) == kDelta, isa = (sym & 7u) == kAdv, cont = sym >> 3;
-                const uint32_t op0 = vq & (e0 ^ 1u), op1 = vq & (e1 ^ 1u);
-                n0 += op0;
-                n1 += op1;
-                a0 += op0 & isa;
-                a1 += op1 & isa;
-                e0 = vq ? (e0 ? cont : isd) : e0;
-                e1 = vq ? (e1 ? cont : isd) : e1;
+                const uint32_t d = (Dv >> (4 * q)) & 1u, c = (Cv >> (4 * q)) & 1u;
+                S0 |= e0 << (4 * q);
+                S1 |= e1 << (4 * q);
+                e0 = e0 ? c : d;
+                e1 = e1 ? c : d;
             }
-            x = RunSum{e0 | (e1 << 1), n0 | (n1 << 16), a0 | (a1 << 16)};
+            const uint32_t A4 = nib_eq(lo3, 0x44444444u), O0 = V4 & ~S0, O1 = V4 & ~S1;
+            const RunSum x{e0 | (e1 << 1), (uint32_t)__popc(O0) | ((uint32_t)__popc(O0 & A4) << 16),
+                           (uint32_t)__popc(O1) | ((uint32_t)__popc(O1 & A4) << 16)};
             incl = wave_scan_run(x);
             excl = dpp_run<kDppWaveShr1>(incl);
         }
-        // this wave's entry state, operation base and ADV base (wf, wn, wa), and the
-        // pass totals (tf, tn, ta): one wavefront has them from its own scan
-        uint32_t wf = kFnId, wn = 0, wa = 0, tf, tn, ta;
+        // this wave's entry state and packed operation / ADV bases for both entry
+        // states (wf, wp0, wp1), and the pass totals (tf, tp0, tp1): one wavefront
+        // has them from its own scan
+        uint32_t wf = kFnId, wp0 = 0, wp1 = 0, tf, tp0, tp1;
         if (NW == 1) {
             tf = (uint32_t)__builtin_amdgcn_readlane((int)incl.f, 63);
-            tn = (uint32_t)__builtin_amdgcn_readlane((int)incl.n, 63);
-            ta = (uint32_t)__builtin_amdgcn_readlane((int)incl.a, 63);
+            tp0 = (uint32_t)__builtin_amdgcn_readlane((int)incl.p0, 63);
+            tp1 = (uint32_t)__builtin_amdgcn_readlane((int)incl.p1, 63);
         } else {
             if (lane == 63) {
                 uint32_t* pub = sh.pub[pb][wave];
                 pub[0] = incl.f;
-                pub[1] = incl.n;
-                pub[2] = incl.a;
+                pub[1] = incl.p0;
+                pub[2] = incl.p1;
             }
             lsync<NT>();
             // the waves' totals, scanned over the first NW lanes (one row of 16)
@@ -689,43 +709,39 @@ __device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const 
             wt = run_then(dpp_run<kDppRowShr + 8>(wt), wt);
             const RunSum we = dpp_run<kDppRowShr + 1>(wt);
             wf = (uint32_t)__builtin_amdgcn_readlane((int)we.f, (int)wave);
-            wn = (uint32_t)__builtin_amdgcn_readlane((int)we.n, (int)wave);
-            wa = (uint32_t)__builtin_amdgcn_readlane((int)we.a, (int)wave);
+            wp0 = (uint32_t)__builtin_amdgcn_readlane((int)we.p0, (int)wave);
+            wp1 = (uint32_t)__builtin_amdgcn_readlane((int)we.p1, (int)wave);
             tf = (uint32_t)__builtin_amdgcn_readlane((int)wt.f, (int)(NW - 1));
-            tn = (uint32_t)__builtin_amdgcn_readlane((int)wt.n, (int)(NW - 1));
-            ta = (uint32_t)__builtin_amdgcn_readlane((int)wt.a, (int)(NW - 1));
+            tp0 = (uint32_t)__builtin_amdgcn_readlane((int)wt.p0, (int)(NW - 1));
+            tp1 = (uint32_t)__builtin_amdgcn_readlane((int)wt.p1, (int)(NW - 1));
         }
         const uint32_t my_e = (wf >> carry) & 1u;
-        const uint32_t my_kb = k_done + ((wn >> (16 * carry)) & kHalf);
-        const uint32_t my_ab = adv_done + ((wa >> (16 * carry)) & kHalf);
+        const uint32_t wp = carry ? wp1 : wp0, tp = carry ? tp1 : tp0;
+        const uint32_t my_kb = k_done + (wp & kHalf);
+        const uint32_t my_ab = adv_done + (wp >> 16);
         const uint32_t k0 = k_done;
-        k_done += (tn >> (16 * carry)) & kHalf;
-        adv_done += (ta >> (16 * carry)) & kHalf;
+        k_done += tp & kHalf;
+        adv_done += tp >> 16;
         carry = (tf >> carry) & 1u;
         pbuf ^= 1u;
-        uint32_t ls = (excl.f >> my_e) & 1u;
+        const uint32_t ls = (excl.f >> my_e) & 1u;
         // this thread's first operation rank and first ADV rank
-        const uint32_t k_first = my_kb + ((excl.n >> (16 * my_e)) & kHalf);
-        const uint32_t a_first = my_ab + ((excl.a >> (16 * my_e)) & kHalf);
+        const uint32_t lp = my_e ? excl.p1 : excl.p0;
+        const uint32_t k_first = my_kb + (lp & kHalf);
+        const uint32_t a_first = my_ab + (lp >> 16);
         uint32_t opm = 0, refm = 0;
         if (wave_on) {
-            // classify the thread's symbols from its entry state: operations, and among
-            // them ADVs, palette (ADV, LAST, DELTA, invalid code), parent and neighbour
-            // operations, and stop bits; each kind is then decoded in a loop of its own,
-            // so a wavefront runs one kind's code at a time
-            uint32_t advm = 0, palm = 0, parm = 0, nbm = 0, stopm = 0;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const uint32_t sym = (word >> (4 * q)) & 15u, vq = (vm >> q) & 1u, op = sym & 7u;
-                const uint32_t isop = vq & (ls ^ 1u);
-                opm |= isop << q;
-                stopm |= (isop & (sym >> 3)) << q;
-                advm |= (isop & (op == kAdv ? 1u : 0u)) << q;
-                palm |= (isop & (op >= kAdv ? 1u : 0u)) << q;
-                parm |= (isop & (op == kParent ? 1u : 0u)) << q;
-                nbm |= (isop & (op - 1u <= kNZ - 1u ? 1u : 0u)) << q;
-                ls = vq ? (ls ? (sym >> 3) : (op == kDelta ? 1u : 0u)) : ls;
-            }
+            // classify the thread's symbols from its entry state (nibble masks):
+            // operations, and among them ADVs, palette (ADV, LAST, DELTA, invalid code:
+            // bit 2 of the code), parent and neighbour operations, and stop bits; each
+            // kind is then decoded in a loop of its own, so a wavefront runs one kind's
+            // code at a time
+            opm = V4 & ~(ls ? S1 : S0);
+            const uint32_t advm = opm & nib_eq(lo3, 0x44444444u);
+            uint32_t palm = opm & (word >> 2) & 0x11111111u;
+            uint32_t parm = opm & nib_eq(lo3, 0u);
+            uint32_t nbm = opm & ~palm & ~parm;
+            uint32_t stopm = opm & C4;
             // operations past the level's node count are an error and write nothing
             if (k_first + (uint32_t)__popc(opm) > expected) {
                 bad = true;
@@ -736,14 +752,14 @@ __device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const 
                 nbm &= km;
                 stopm |= ~km;
             }
-            // rank of the operation at position q, its ADV rank, and its node
-            auto k_at = [&](uint32_t q) -> uint32_t { return k_first + (uint32_t)__popc(opm & ((1u << q) - 1u)); };
-            auto a_at = [&](uint32_t q) -> uint32_t { return a_first + (uint32_t)__popc(advm & ((1u << q) - 1u)); };
+            // rank of the operation at bit position b = 4q, its ADV rank, and its node
+            auto k_at = [&](uint32_t b) -> uint32_t { return k_first + (uint32_t)__popc(opm & ((1u << b) - 1u)); };
+            auto a_at = [&](uint32_t b) -> uint32_t { return a_first + (uint32_t)__popc(advm & ((1u << b) - 1u)); };
             auto node_of = [&](uint32_t kq) -> uint32_t { return i ? ((parent_of(kq) << 3) | (kq & 7u)) : 0u; };
             // palette: ADV -> a, LAST -> a - 1, DELTA -> a - delta, the entries following in the window
             for (uint32_t m = palm; m; m &= m - 1u) {
-                const uint32_t q = (uint32_t)__builtin_ctz(m), kq = k_at(q), aq = a_at(q);
-                const uint32_t op = (word >> (4 * q)) & 7u;
+                const uint32_t b = (uint32_t)__builtin_ctz(m), q = b >> 2, kq = k_at(b), aq = a_at(b);
+                const uint32_t op = (word >> b) & 7u;
                 uint32_t v = FIN;
                 bool err = false;
                 if (op == kAdv) {
@@ -780,7 +796,7 @@ __device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const 
             }
             // parent copies
             for (uint32_t m = parm; m; m &= m - 1u) {
-                const uint32_t q = (uint32_t)__builtin_ctz(m), kq = k_at(q);
+                const uint32_t kq = k_at((uint32_t)__builtin_ctz(m));
                 const uint32_t pn = parent_of(kq);
                 uint32_t v = FIN;
                 if (i == 0) bad = true;
@@ -791,8 +807,8 @@ __device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const 
             // neighbour copies: an implied target holds its parent's value, an explicit one of
             // an earlier pass its final value, one of this pass becomes a reference
             for (uint32_t m = nbm; m; m &= m - 1u) {
-                const uint32_t q = (uint32_t)__builtin_ctz(m), kq = k_at(q);
-                const uint32_t op = (word >> (4 * q)) & 7u;
+                const uint32_t b = (uint32_t)__builtin_ctz(m), kq = k_at(b);
+                const uint32_t op = (word >> b) & 7u;
                 const uint32_t p = node_of(kq);
                 const uint32_t am = op == kNX ? mx : op == kNY ? my : mz;
                 uint32_t v = FIN;
@@ -813,7 +829,7 @@ __device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const 
                             v = kt < k0 ? read_slot(ti) : ti;
                         }
                     }
-                    refm |= (v & FIN) ? 0u : (1u << q);
+                    refm |= (v & FIN) ? 0u : (1u << b);
                 }
                 write_slot(slot_of(kq, p), v);
             }
@@ -830,8 +846,8 @@ __device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const 
         // references within the pass: chase to a final value (targets precede
         // their sources, so every chain ends within the pass's operations)
         for (uint32_t m = refm; m; m &= m - 1u) {
-            const uint32_t q = (uint32_t)__builtin_ctz(m);
-            const uint32_t kq = k_first + (uint32_t)__popc(opm & ((1u << q) - 1u));
+            const uint32_t b = (uint32_t)__builtin_ctz(m);
+            const uint32_t kq = k_first + (uint32_t)__popc(opm & ((1u << b) - 1u));
             const uint32_t pq = i ? ((parent_of(kq) << 3) | (kq & 7u)) : 0u;
             const uint32_t me = slot_of(kq, pq);
             const uint32_t lim = KIND == 0 ? nodes : KIND == 1 ? k_done : (1u << 18);
