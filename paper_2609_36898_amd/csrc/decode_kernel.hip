@@ -810,9 +810,22 @@ __device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const 
                 const uint32_t b = (uint32_t)__builtin_ctz(m), kq = k_at(b);
                 const uint32_t op = (word >> b) & 7u;
                 const uint32_t p = node_of(kq);
-                const uint32_t am = op == kNX ? mx : op == kNY ? my : mz;
+                const uint32_t am = mx << ((op - 1u) & 3u);  // NX, NY, NZ: the x, y or z bits
                 uint32_t v = FIN;
-                if (!(p & am)) {
+                if (KIND == 1) {
+                    // level 5 without branches: the target's implied value (its level-4
+                    // parent's) and its explicit slot are both read, then selected; a
+                    // node at coordinate 0 (no neighbour) reads in-range garbage
+                    const uint32_t pa = p & am;
+                    const uint32_t tn = ((pa - 1u) & am) | (p & ~am), tq = tn >> 3;
+                    const uint32_t ew = st.E[ebase(4) + (tq >> 5)];
+                    const uint32_t kt = 8u * (st.wpre[ebase(4) + (tq >> 5)] +
+                                              (uint32_t)__popc(ew & ((1u << (tq & 31)) - 1u))) + (tn & 7u);
+                    const uint32_t implied = full_p[tq], got = st.c5[kt < k0 ? kt : 0u];
+                    v = !pa ? FIN : !((ew >> (tq & 31)) & 1u) ? implied : kt < k0 ? got : kt;
+                    bad = bad || !pa;
+                    refm |= (v & FIN) ? 0u : (1u << b);
+                } else if (!(p & am)) {
                     bad = true;
                 } else {
                     const uint32_t tn = (((p & am) - 1u) & am) | (p & ~am);
@@ -999,10 +1012,10 @@ __device__ __forceinline__ void write_labels(const Params& P, Shared& sh, const 
         const uint64_t e0 = ((uint64_t)(2 * qz) * S + 2 * qy) * S + 4 * px;
         // palette indices of the 8 children of each of the two nodes (child c = x | y << 1 | z << 2)
         uint32_t ix[2][8];
+        const uint32_t q0 = spread3(2 * px) | (spread3(qy) << 1) | (spread3(qz) << 2);
 #pragma unroll
         for (int hx = 0; hx < 2; ++hx) {
-            const uint32_t qx = 2 * px + hx;
-            const uint32_t q = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
+            const uint32_t q = q0 | (uint32_t)hx;  // the x neighbour differs in bit 0
             if (t == 5) {
                 if (st.ebit(4, q)) {
                     const V* c = st.c5 + 8 * st.rank(4, q);
