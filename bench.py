@@ -58,15 +58,16 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(workload: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, when it
-    was taken on the current kernel source (else None)."""
+def profiled_traffic(workload: str, key: str = "hbm_bytes_per_launch"):
+    """HBM bytes per launch (or, key hbm_bytes_total, over all decode dispatches
+    of the profiled process) from the committed rocprofv3 counter summary, when
+    it was taken on the current kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", "decode_kernel_%s_traffic.txt" % workload)
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", txt)
-    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    m_bytes = re.search(key + r":\s*([0-9.eE+]+)", txt)
     if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
         return None
     return float(m_bytes.group(1))
@@ -381,6 +382,13 @@ def measure_served(wl: Workload, args, dev):
     m_starts = starts[nw:] - starts[nw]
     lod_hist = np.bincount(lods, minlength=5).tolist()
 
+    # algorithmic bytes of every decode dispatch this process makes (all servers)
+    proc = {"alg": 0.0, "dispatches": 0}
+
+    def account(s):
+        proc["alg"] += s["record_bytes"] + 4.0 * s["decoded_elements"]
+        proc["dispatches"] += s["batches"]
+
     def run(rate):
         srv = P.csgv.csgv_server(dv.info, dv.tensor, cache, cache_elems, n_streams=args.serve_streams,
                                  max_batch=args.serve_batch, n_shards=args.serve_shards)
@@ -389,6 +397,7 @@ def measure_served(wl: Workload, args, dev):
         arr = np.zeros(nm) if rate is None else (unit_arr[nw:] - unit_arr[nw]) / rate
         rec = srv.run(m_ids, m_lods, m_starts, arr)
         s1 = srv.stats()
+        account(s1)
         srv.destroy()
         d = {k: s1[k] - s0[k] for k in s1 if k not in ("cache_top", "resident", "pinned", "max_batch_seen")}
         span = float(rec["t_done"].max())
@@ -440,6 +449,7 @@ def measure_served(wl: Workload, args, dev):
         c_ids.append(rid)
         c_lods.append(rl)
         srv.release(q)
+    account(srv.stats())
     srv.destroy()
     c_ids, c_lods = np.concatenate(c_ids), np.concatenate(c_lods)
     offs, total = P.dense_offsets(np.full(len(c_ids), 5, np.uint8), c_lods)
@@ -449,17 +459,27 @@ def measure_served(wl: Workload, args, dev):
     del cache, dv
     torch.cuda.empty_cache()
 
+    # HBM traffic: the profiled process's decode dispatches moved hbm_total bytes for the
+    # algorithmic bytes proc["alg"] of the same work (the served pairs do not depend on
+    # timing); that ratio, applied to a saturation launch, is its traffic per launch
+    alg_launch = alg / max(sat_d["batches"], 1)
+    hbm_total = profiled_traffic(wl.name, "hbm_bytes_total")
+    ratio = hbm_total / proc["alg"] if hbm_total and proc["alg"] > 0 else None
     res = {
         "value": sat["decoded_gvoxel_s"], "ms_per_step": round(1e3 * sat["seconds"] / nm, 4),
         "config": dict(wl.config, warmup_requests=nw, measured_requests=nm, lod_histogram=lod_hist,
                        streams=args.serve_streams, max_batch=args.serve_batch, shards=args.serve_shards),
         "roofline": {"bound": "hbm", "achieved": round(kgbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(kgbs / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(wl.name),
+                     "frac": round(kgbs / HBM_PEAK_GBS, 4),
+                     "traffic": round(ratio * alg_launch, 1) if ratio else None,
+                     "traffic_over_alg": round(ratio, 4) if ratio else None,
                      "kernel": DECODE_KERNEL, "kernel_ms_total": round(sat_d["kernel_ms"], 3),
                      "launches": sat_d["batches"], "alg_bytes_total": alg,
-                     "alg_bytes_per_launch": round(alg / max(sat_d["batches"], 1), 1),
-                     "note": "over the saturation run: sum of algorithmic bytes / sum of decode-kernel times; "
-                             "traffic = mean HBM bytes per decode dispatch of a profiled served run"},
+                     "alg_bytes_per_launch": round(alg_launch, 1),
+                     "process_alg_bytes": proc["alg"], "process_dispatches": proc["dispatches"],
+                     "note": "over the saturation run: sum of algorithmic bytes / sum of decode-kernel times "
+                             "(launches of several shards overlap); traffic = the profiled process's HBM bytes "
+                             "over all decode dispatches / its algorithmic bytes, times alg_bytes_per_launch"},
         "served": {"saturation": sat, **loads, "checked_requests": len(check), "checked_pairs": int(len(c_ids))},
         "bit_exact": exact and sat["all_ok"] and all(v["all_ok"] for v in loads.values()),
         "shape": {"wg_size": "default", "sort_tasks": "default"},
@@ -668,6 +688,8 @@ def summarize_traffic(fetch_dir: str, write_dir: str, workload: str) -> str:
     kw = CALIB_COPY_BYTES / 1024.0 / copy_w
     df, dw = float(np.mean(f[DECODE_KERNEL])), float(np.mean(w[DECODE_KERNEL]))
     rd, wr = df * kf * 1024.0, dw * kw * 1024.0
+    # over all decode dispatches of a run (each counter run does the same work)
+    tot = (float(np.sum(f[DECODE_KERNEL])) * kf + float(np.sum(w[DECODE_KERNEL])) * kw) * 1024.0
     return "\n".join([
         "workload: %s" % workload,
         "kernel_source_sha256_16: %s" % kernel_source_hash(),
@@ -677,6 +699,7 @@ def summarize_traffic(fetch_dir: str, write_dir: str, workload: str) -> str:
         "decode_kernel FETCH_SIZE mean %.1f KiB -> read bytes %.0f" % (df, rd),
         "decode_kernel WRITE_SIZE mean %.1f KiB -> written bytes %.0f" % (dw, wr),
         "hbm_bytes_per_launch: %.0f" % (rd + wr),
+        "hbm_bytes_total: %.0f" % tot,
     ]) + "\n"
 
 
@@ -700,7 +723,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=10000, help="measured requests of the served workload")
     ap.add_argument("--serve-warmup", type=int, default=1000, help="warm-up requests before each served run")
     ap.add_argument("--serve-streams", type=int, default=2, help="HIP streams per cache shard")
-    ap.add_argument("--serve-shards", type=int, default=8, help="cache shards (host threads) of the server")
+    ap.add_argument("--serve-shards", type=int, default=16, help="cache shards (host threads) of the server")
     ap.add_argument("--serve-batch", type=int, default=4096)
     ap.add_argument("--serve-check", type=int, default=24, help="pinned requests checked against the oracle")
     ap.add_argument("--summarize-rocprof", default=None, metavar="DIR")
