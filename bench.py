@@ -724,7 +724,7 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=1000, help="warm-up requests before each served run")
     ap.add_argument("--serve-streams", type=int, default=2, help="HIP streams per cache shard")
     ap.add_argument("--serve-shards", type=int, default=16, help="cache shards (host threads) of the server")
-    ap.add_argument("--serve-batch", type=int, default=4096)
+    ap.add_argument("--serve-batch", type=int, default=16384, help="tasks per served batch (per shard stream)")
     ap.add_argument("--serve-check", type=int, default=24, help="pinned requests checked against the oracle")
     ap.add_argument("--summarize-rocprof", default=None, metavar="DIR")
     ap.add_argument("--summarize-traffic", nargs=2, default=None, metavar=("FETCH_DIR", "WRITE_DIR"))

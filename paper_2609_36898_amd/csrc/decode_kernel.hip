@@ -937,10 +937,19 @@ __device__ __forceinline__ void decode_levels(const Params& P, Shared& sh, const
 }
 
 // ------------------------------------------------------------------ output
+// Decoded labels are written once and not read again by the kernel: vector
+// stores carry the non-temporal hint, so they do not displace the records and
+// symbols other work-groups still read from L2.
+typedef uint32_t u32x4 __attribute__((vector_size(16)));
+__device__ __forceinline__ void st16_nt(void* p, uint4 v) {
+    const u32x4 w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, (u32x4*)p);
+}
+
 template <typename LT>
 __device__ __forceinline__ void store4(LT* o, LT a, LT b, LT c, LT d, bool vec) {
     if (sizeof(LT) == 4) {
-        if (vec) *(uint4*)o = make_uint4((uint32_t)a, (uint32_t)b, (uint32_t)c, (uint32_t)d);
+        if (vec) st16_nt(o, make_uint4((uint32_t)a, (uint32_t)b, (uint32_t)c, (uint32_t)d));
         else {
             o[0] = a;
             o[1] = b;
@@ -949,8 +958,8 @@ __device__ __forceinline__ void store4(LT* o, LT a, LT b, LT c, LT d, bool vec) 
         }
     } else {
         if (vec) {
-            ((uint4*)o)[0] = make_uint4((uint32_t)a, (uint32_t)((uint64_t)a >> 32), (uint32_t)b, (uint32_t)((uint64_t)b >> 32));
-            ((uint4*)o)[1] = make_uint4((uint32_t)c, (uint32_t)((uint64_t)c >> 32), (uint32_t)d, (uint32_t)((uint64_t)d >> 32));
+            st16_nt((uint4*)o, make_uint4((uint32_t)a, (uint32_t)((uint64_t)a >> 32), (uint32_t)b, (uint32_t)((uint64_t)b >> 32)));
+            st16_nt((uint4*)o + 1, make_uint4((uint32_t)c, (uint32_t)((uint64_t)c >> 32), (uint32_t)d, (uint32_t)((uint64_t)d >> 32)));
         } else {
             o[0] = a;
             o[1] = b;
@@ -991,7 +1000,8 @@ __device__ __forceinline__ void write_labels(const Params& P, Shared& sh, const 
             const uint32_t n = S * S * S;
             for (uint32_t v = threadIdx.x; v < n; v += NT) {
                 const uint32_t x = v & (S - 1), y = (v >> t) & (S - 1), z = v >> (2 * t);
-                out[v] = pal_get<LT, PAL_LDS>(pal, g[spread3(x) | (spread3(y) << 1) | (spread3(z) << 2)] & VIDX, pc);
+                const LT l = pal_get<LT, PAL_LDS>(pal, g[spread3(x) | (spread3(y) << 1) | (spread3(z) << 2)] & VIDX, pc);
+                __builtin_nontemporal_store(l, out + v);
             }
             return;
         }
@@ -1079,7 +1089,7 @@ __device__ __forceinline__ void write_indices(const Params& P, Shared& sh, const
             }
             acc |= idx << (q * bits);
         }
-        out[w] = acc;
+        __builtin_nontemporal_store(acc, out + w);
     }
 }
 
