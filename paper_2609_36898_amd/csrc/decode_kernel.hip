@@ -895,6 +895,19 @@ __device__ __forceinline__ void decode_levels(const Params& P, Shared& sh, const
         for (uint32_t i = 0; i <= tw; ++i) {
             uint32_t expected = 1;
             if (i == 0) {
+                // Level 0 is one node whose only valid operation is PALETTE_ADV (entry
+                // 0), with or without a stop bit: take that case directly; anything
+                // else goes through the general pass, which reports the error.
+                const uint32_t s0 = nib[0] & 15u;
+                if (sh.h.sym_end[0] == 1u && (s0 & 7u) == kAdv && sh.h.pc > 0u) {
+                    if (threadIdx.x == 0) {
+                        st.full[fbase(0)] = (V)Slot<V>::kFinal;
+                        if (t > 0) st.E[ebase(0)] = (s0 & 8u) ? 0u : 1u;
+                    }
+                    adv_done = 1;
+                    lsync<64>();
+                    continue;
+                }
                 if (t > 0 && threadIdx.x == 0) st.E[ebase(0)] = 0;
                 lsync<64>();
             } else {
