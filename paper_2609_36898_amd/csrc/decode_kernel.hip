@@ -84,6 +84,7 @@ struct Shared {
     TaskHdr hn;  // the work-group's next task, parsed ahead
     uint32_t err;
     uint32_t tab_ok;                     // the rANS table is in LDS from an earlier task
+    uint32_t prog[4];                    // per rANS lane group: symbols out so far (release/acquire)
     uint32_t nexp;                       // expanding nodes of the parent level of the next level
     uint32_t adv;                        // PALETTE_ADV operations decoded so far (handed between phases)
     uint32_t pub[2][kMaxWaves][4];       // per pass and wave: run summary (f, n, a)
@@ -362,33 +363,42 @@ __device__ __forceinline__ void rans_decode(const Params& P, Shared& sh, const u
     }
 }
 
-// The same decode with the record's words staged in LDS (`stage`, the level
-// grids and slot area, idle until the levels start) and the symbols written
-// to LDS at `nl`: a lane that renormalises reads its word from LDS, and no
-// round waits on a global store.  With `nib` set, the symbols then reach it
-// in one coalesced copy.  The caller checks that words and symbols fit.
+// Copy the record's rANS words into LDS at `wl` (no barrier) and return this
+// thread's state for its wavefront's first lane group.
 template <int NT>
-__device__ __forceinline__ void rans_decode_lds(const Params& P, Shared& sh, const uint32_t* tab, uint8_t* stage,
-                                                uint8_t* nl, uint8_t* nib) {
-    const TaskHdr& h = sh.h;
+__device__ __forceinline__ uint32_t rans_stage_words(const Params& P, const TaskHdr& h, uint16_t* wl) {
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     const uint32_t W = 1u << h.log2W, G = (W + 63) / 64, lanes = W < 64 ? W : 64;
-    const uint32_t nsym = h.nsym, tw = h.gstart[G - 1] + h.gw[G - 1];
-    uint16_t* const wl = (uint16_t*)stage;
+    const uint32_t tw = h.gstart[G - 1] + h.gw[G - 1];
     const uint16_t* const wg = (const uint16_t*)(P.vol + h.pay_off);
     const uint32_t* states = (const uint32_t*)(P.vol + h.states_off);
-    // the state of this wave's first lane group is loaded along with the words
-    uint32_t x0 = wave < G && lane < lanes ? states[64 * wave + lane] : 0u;
+    const uint32_t x0 = wave < G && lane < lanes ? states[64 * wave + lane] : 0u;
     for (uint32_t q = tid; q < tw / 2u; q += NT) ((uint32_t*)wl)[q] = ((const uint32_t*)wg)[q];
     if ((tw & 1u) && tid == 0) wl[tw - 1u] = wg[tw - 1u];
-    __syncthreads();
+    return x0;
+}
+
+// The rounds of the decode from words staged in LDS at `wl` (after a barrier),
+// symbols written to LDS at `nl`: a lane that renormalises reads its word from
+// LDS, and no round waits on a global store.  Wavefront w decodes lane groups
+// w, w + NW, ...  With `mark`, lane 0 publishes in sh.prog[g], with release
+// order, that group g's symbols below index `mark` are out as soon as they are
+// (its next round would start at or past `mark`), and ~0 when the group is done.
+template <int NT>
+__device__ __forceinline__ void rans_rounds(const Params& P, Shared& sh, const uint32_t* tab, const uint16_t* wl,
+                                            uint8_t* nl, uint32_t x0, uint32_t mark) {
+    const TaskHdr& h = sh.h;
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    const uint32_t W = 1u << h.log2W, G = (W + 63) / 64, lanes = W < 64 ? W : 64;
+    const uint32_t nsym = h.nsym;
+    const uint32_t* states = (const uint32_t*)(P.vol + h.states_off);
     for (uint32_t g = wave; g < G; g += NT / 64) {
         const bool active = lane < lanes;
         const uint32_t gcount = h.gw[g], gbase = h.gstart[g];
         uint32_t x = g == wave ? x0 : active ? states[64 * g + lane] : 0u;
         uint32_t gpos = 0, pend = 0;
         const uint32_t gcm1 = gcount ? gcount - 1u : 0u;  // word reads stay inside the group
-        bool bad = false;
+        bool bad = false, marked = mark == 0;
         __builtin_amdgcn_s_waitcnt(0);
         // a round without branches: every lane looks its state up and reads a
         // word; a lane past the symbols keeps its state
@@ -417,13 +427,30 @@ __device__ __forceinline__ void rans_decode_lds(const Params& P, Shared& sh, con
                     nl[j >> 1] = (uint8_t)(pend | (s << 4));
                 }
             }
+            if (!marked && r0 + W >= mark) {
+                marked = true;
+                if (lane == 0) __hip_atomic_store(&sh.prog[g], mark, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
         }
         if (__ballot(bad) && lane == 0) atomicOr(&sh.err, 1u);
+        if (mark && lane == 0) __hip_atomic_store(&sh.prog[g], 0xFFFFFFFFu, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
+}
+
+// The decode with the record's words staged in LDS (`stage`, the level grids
+// and slot area, idle until the levels start) and the symbols in LDS at `nl`;
+// with `nib` set, the symbols then reach it in one coalesced copy.  The caller
+// checks that words and symbols fit.
+template <int NT>
+__device__ __forceinline__ void rans_decode_lds(const Params& P, Shared& sh, const uint32_t* tab, uint8_t* stage,
+                                                uint8_t* nl, uint8_t* nib) {
+    const uint32_t x0 = rans_stage_words<NT>(P, sh.h, (uint16_t*)stage);
+    __syncthreads();
+    rans_rounds<NT>(P, sh, tab, (const uint16_t*)stage, nl, x0, 0u);
     if (nib) {
         __syncthreads();
-        const uint32_t nw = ((nsym + 1u) / 2u + 3u) / 4u;
-        for (uint32_t q = tid; q < nw; q += NT) ((uint32_t*)nib)[q] = ((const uint32_t*)nl)[q];
+        const uint32_t nw = ((sh.h.nsym + 1u) / 2u + 3u) / 4u;
+        for (uint32_t q = threadIdx.x; q < nw; q += NT) ((uint32_t*)nib)[q] = ((const uint32_t*)nl)[q];
     }
 }
 
@@ -509,7 +536,7 @@ __device__ __forceinline__ void level_prefix(Shared& sh, const Store<V>& st, uin
 
 template <int NT, typename V, bool BIG, bool LIST_LDS, bool PL5>
 __device__ __forceinline__ void level_fill(Shared& sh, const Store<V>& st, uint32_t i, uint32_t t) {
-    const uint32_t tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x & (NT - 1);  // (NT = 64: the calling wavefront's lane)
     const uint32_t pl = i - 1, pn = 1u << (3 * pl);
     const uint32_t* const Ep = PL5 ? st.E5 : st.E + ebase(pl);
     const uint16_t* const Wp = PL5 ? st.wpre5 : st.wpre + ebase(pl);
@@ -597,7 +624,7 @@ template <int NT, int KIND, typename V, bool BIG, bool LIST_LDS>
 __device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const Store<V>& st, const uint8_t* nib, uint32_t i,
                              uint32_t expected, uint32_t& adv_done, uint32_t& pbuf) {
     constexpr uint32_t NW = NT / 64;
-    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    const uint32_t tid = threadIdx.x & (NT - 1), lane = lane_id(), wave = tid >> 6;
     const uint32_t t = sh.h.t, pc = sh.h.pc;
     const uint32_t nodes = 1u << (3 * i);
     // final flag of this level's slots (level 6 slots are always u32)
@@ -880,56 +907,67 @@ __device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const 
     if ((k_done != expected || carry != 0) && tid == 0) sh.err = 1u;
 }
 
+// Levels 0..min(t, 2) (at most 73 nodes) decoded by the calling wavefront
+// alone, with wave barriers; then the parent prefix of level 3 when the cube
+// has one, and the ADV count in sh.adv.
+template <typename V, bool BIG, bool LIST_LDS>
+__device__ __forceinline__ void small_levels(const Params& P, Shared& sh, const Store<V>& st, const uint8_t* nib) {
+    const uint32_t t = sh.h.t, tw = t < 2u ? t : 2u, lane = lane_id();
+    uint32_t adv_done = 0, pbuf = 0;
+    for (uint32_t i = 0; i <= tw; ++i) {
+        uint32_t expected = 1;
+        if (i == 0) {
+            // Level 0 is one node whose only valid operation is PALETTE_ADV (entry
+            // 0), with or without a stop bit: take that case directly; anything
+            // else goes through the general pass, which reports the error.
+            const uint32_t s0 = nib[0] & 15u;
+            if (sh.h.sym_end[0] == 1u && (s0 & 7u) == kAdv && sh.h.pc > 0u) {
+                if (lane == 0) {
+                    st.full[fbase(0)] = (V)Slot<V>::kFinal;
+                    if (t > 0) st.E[ebase(0)] = (s0 & 8u) ? 0u : 1u;
+                }
+                adv_done = 1;
+                lsync<64>();
+                continue;
+            }
+            if (t > 0 && lane == 0) st.E[ebase(0)] = 0;
+            lsync<64>();
+        } else {
+            level_prefix<V, false>(sh, st, i - 1);
+            lsync<64>();
+            expected = 8 * sh.nexp;
+            level_fill<64, V, BIG, LIST_LDS, false>(sh, st, i, t);
+        }
+        level_passes<64, 0, V, BIG, LIST_LDS>(P, sh, st, nib, i, expected, adv_done, pbuf);
+        lsync<64>();
+        if (sh.err) break;
+    }
+    if (!sh.err && t > tw) level_prefix<V, false>(sh, st, tw);
+    if (lane == 0) sh.adv = adv_done;
+}
+
 // Decode levels 0..t; on return all slots of level t are final unless sh.err.
-// Levels 0..2 (at most 73 nodes) are decoded by wavefront 0 alone, with wave
-// barriers; the other wavefronts wait at the work-group barrier that follows.
-// From level 3 on, all threads decode; wavefront 0 computes the next level's
-// parent prefix after a level's last pass, before the barrier that ends it.
+// Levels 0..2 are decoded by one wavefront (wavefront 0 here, unless `small_done`:
+// they were decoded during the rANS decode), the other wavefronts wait at the
+// work-group barrier that follows.  From level 3 on, all threads decode;
+// wavefront 0 computes the next level's parent prefix after a level's last
+// pass, before the barrier that ends it.
 template <int NT, typename V, bool BIG, bool LIST_LDS>
 __device__ __forceinline__ void decode_levels(const Params& P, Shared& sh, const Store<V>& st, const uint8_t* nib,
-                                              Ahead& ah) {
+                                              Ahead& ah, bool small_done) {
     const uint32_t t = sh.h.t, wave = threadIdx.x >> 6;
-    const uint32_t tw = t < 2u ? t : 2u;  // last level of wavefront 0 alone
-    uint32_t adv_done = 0, pbuf = 0;
-    if (wave == 0) {
-        for (uint32_t i = 0; i <= tw; ++i) {
-            uint32_t expected = 1;
-            if (i == 0) {
-                // Level 0 is one node whose only valid operation is PALETTE_ADV (entry
-                // 0), with or without a stop bit: take that case directly; anything
-                // else goes through the general pass, which reports the error.
-                const uint32_t s0 = nib[0] & 15u;
-                if (sh.h.sym_end[0] == 1u && (s0 & 7u) == kAdv && sh.h.pc > 0u) {
-                    if (threadIdx.x == 0) {
-                        st.full[fbase(0)] = (V)Slot<V>::kFinal;
-                        if (t > 0) st.E[ebase(0)] = (s0 & 8u) ? 0u : 1u;
-                    }
-                    adv_done = 1;
-                    lsync<64>();
-                    continue;
-                }
-                if (t > 0 && threadIdx.x == 0) st.E[ebase(0)] = 0;
-                lsync<64>();
-            } else {
-                level_prefix<V, false>(sh, st, i - 1);
-                lsync<64>();
-                expected = 8 * sh.nexp;
-                level_fill<64, V, BIG, LIST_LDS, false>(sh, st, i, t);
-            }
-            level_passes<64, 0, V, BIG, LIST_LDS>(P, sh, st, nib, i, expected, adv_done, pbuf);
-            lsync<64>();
-            if (sh.err) break;
+    const uint32_t tw = t < 2u ? t : 2u;  // last level of the single wavefront
+    if (!small_done) {
+        if (wave == 0) {
+            small_levels<V, BIG, LIST_LDS>(P, sh, st, nib);
+        } else if (threadIdx.x == NT - 64 && !ah.done) {
+            parse_ahead(P, sh.hn, ah.jt);
+            ah.done = true;
         }
-        if (!sh.err && t > tw) level_prefix<V, false>(sh, st, tw);
-        if (threadIdx.x == 0) sh.adv = adv_done;
-    } else if (threadIdx.x == NT - 64 && !ah.done) {
-        parse_ahead(P, sh.hn, ah.jt);
-        ah.done = true;
+        __syncthreads();
     }
-    __syncthreads();
     if (sh.err) return;
-    adv_done = sh.adv;
-    pbuf = 0;
+    uint32_t adv_done = sh.adv, pbuf = 0;
     for (uint32_t i = tw + 1; i <= t; ++i) {
         const uint32_t expected = 8 * sh.nexp;
         if (i <= 5) level_fill<NT, V, BIG, LIST_LDS, false>(sh, st, i, t);
@@ -1120,9 +1158,8 @@ __device__ __forceinline__ void write_output(const Params& P, Shared& sh, const 
 }
 
 // ------------------------------------------------------------------ a task
-template <int NT, typename V, bool BIG>
-__device__ __forceinline__ void run_levels(const Params& P, Shared& sh, uint16_t* slots_lds, uint8_t* scratch, const uint8_t* nib,
-                                           Ahead& ah) {
+template <typename V, bool BIG>
+__device__ __forceinline__ Store<V> make_store(const Params& P, Shared& sh, uint16_t* slots_lds, uint8_t* scratch) {
     const TaskHdr& h = sh.h;
     Store<V> st;
     st.E = sh.E;
@@ -1141,8 +1178,16 @@ __device__ __forceinline__ void run_levels(const Params& P, Shared& sh, uint16_t
         st.full = (V*)sh.G;
         st.c5 = (V*)slots_lds;
     }
-    if (!BIG && h.t <= 5) decode_levels<NT, V, BIG, true>(P, sh, st, nib, ah);
-    else decode_levels<NT, V, BIG, false>(P, sh, st, nib, ah);
+    return st;
+}
+
+template <int NT, typename V, bool BIG>
+__device__ __forceinline__ void run_levels(const Params& P, Shared& sh, uint16_t* slots_lds, uint8_t* scratch, const uint8_t* nib,
+                                           Ahead& ah, bool small_done) {
+    const TaskHdr& h = sh.h;
+    const Store<V> st = make_store<V, BIG>(P, sh, slots_lds, scratch);
+    if (!BIG && h.t <= 5) decode_levels<NT, V, BIG, true>(P, sh, st, nib, ah, small_done);
+    else decode_levels<NT, V, BIG, false>(P, sh, st, nib, ah, small_done);
     if (sh.err) return;
     // palette staging for the output pass (the parent list is no longer needed);
     // a cube of side <= 8 reads its few labels straight from the record
@@ -1170,7 +1215,7 @@ __device__ __forceinline__ void decode_task(const Params& P, Shared& sh, uint16_
     constexpr uint32_t kListMax4 = 1024;
     const bool sym_lds = h.t <= 4 && (h.nsym + 1u) / 2u + 4u <= kUBytes - kListMax4;
     uint8_t* const nib = sym_lds ? sh.U + kListMax4 : scratch + kScrSym;
-    bool tab_used = false;
+    bool tab_used = false, small_done = false;
     if (h.coder == kRaw4) {
         const uint32_t bytes = (h.nsym + 1u) / 2u, words = bytes / 4u;
         const uint32_t* src = (const uint32_t*)(P.vol + h.pay_off);
@@ -1195,8 +1240,44 @@ __device__ __forceinline__ void decode_task(const Params& P, Shared& sh, uint16_
         const uint32_t words_bytes = (2u * tw + 15u) & ~15u;
         const uint32_t sym_bytes = ((h.nsym + 1u) / 2u + 3u) / 4u * 4u;
         // symbols bound for the parent list area: the staged words must end before it
-        const uint32_t nl_at = (uint32_t)(offsetof(Shared, U) - offsetof(Shared, G)) + kListMax4;
-        if (sym_lds && words_bytes <= nl_at) rans_decode_lds<NT>(P, sh, tab, stage, nib, nullptr);
+        const uint32_t u_at = (uint32_t)(offsetof(Shared, U) - offsetof(Shared, G));
+        const uint32_t nl_at = u_at + kListMax4;
+        // Overlap, for a fast-path cube with a level 3 whose lane groups leave a
+        // wavefront free: words staged after the grids of levels 0..2, symbols at
+        // the end of the stage (clear of the level 1..2 parent lists).  Wavefronts
+        // 0..G-1 decode the lane groups, wavefront G decodes levels 0..2 as soon
+        // as every group is past their symbols, and the last wavefront, when it
+        // is not G, parses the next task.
+        constexpr uint32_t kLoGrid = 256;  // bytes of the level 0..2 grids
+        const uint32_t G1 = ((1u << h.log2W) + 63u) / 64u;
+        // (two or more lanes: a round writes whole bytes of symbol pairs)
+        const bool overlap = G1 < NT / 64 && h.log2W >= 1u && !sym_lds && !h.big && h.t >= 3 && h.t <= 5 &&
+                             kLoGrid + words_bytes <= u_at && sym_bytes + u_at + 48u <= stage_bytes;
+        if (overlap) {
+            const uint32_t wave = threadIdx.x >> 6;
+            uint16_t* const wl = (uint16_t*)(stage + kLoGrid);
+            uint8_t* const nl = stage + ((stage_bytes - sym_bytes) & ~15u);
+            if (threadIdx.x < 4) sh.prog[threadIdx.x] = 0;
+            const uint32_t x0 = rans_stage_words<NT>(P, h, wl);
+            __syncthreads();
+            const uint32_t need = h.sym_end[2];
+            if (wave < G1) {
+                rans_rounds<NT>(P, sh, tab, wl, nl, x0, need ? need : 1u);
+            } else if (wave == G1) {
+                // bounded: every group publishes ~0 when its rounds end
+                for (uint32_t g = 0; g < G1; ++g)
+                    while (__hip_atomic_load(&sh.prog[g], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < need)
+                        __builtin_amdgcn_s_sleep(1);
+                small_levels<uint16_t, false, true>(P, sh, make_store<uint16_t, false>(P, sh, slots_lds, scratch), nl);
+            } else if (threadIdx.x == NT - 64 && !ah.done) {
+                parse_ahead(P, sh.hn, ah.jt);
+                ah.done = true;
+            }
+            __syncthreads();
+            const uint32_t nw = ((h.nsym + 1u) / 2u + 3u) / 4u;
+            for (uint32_t q = threadIdx.x; q < nw; q += NT) ((uint32_t*)nib)[q] = ((const uint32_t*)nl)[q];
+            small_done = true;
+        } else if (sym_lds && words_bytes <= nl_at) rans_decode_lds<NT>(P, sh, tab, stage, nib, nullptr);
         else if (!sym_lds && words_bytes + sym_bytes <= stage_bytes)
             rans_decode_lds<NT>(P, sh, tab, stage, stage + words_bytes, nib);
         else rans_decode<NT>(P, sh, tab, nib);
@@ -1205,8 +1286,8 @@ __device__ __forceinline__ void decode_task(const Params& P, Shared& sh, uint16_
     // level 5 of a fast-path task overwrites the table
     const bool tab_lost = !h.big && h.t >= 5;
     if (!sh.err) {
-        if (h.big) run_levels<NT, uint32_t, true>(P, sh, slots_lds, scratch, nib, ah);
-        else run_levels<NT, uint16_t, false>(P, sh, slots_lds, scratch, nib, ah);
+        if (h.big) run_levels<NT, uint32_t, true>(P, sh, slots_lds, scratch, nib, ah, small_done);
+        else run_levels<NT, uint16_t, false>(P, sh, slots_lds, scratch, nib, ah, small_done);
     }
     __syncthreads();
     if (sh.err) {
