@@ -1243,20 +1243,21 @@ __device__ __forceinline__ void decode_task(const Params& P, Shared& sh, uint16_
         const uint32_t u_at = (uint32_t)(offsetof(Shared, U) - offsetof(Shared, G));
         const uint32_t nl_at = u_at + kListMax4;
         // Overlap, for a fast-path cube with a level 3 whose lane groups leave a
-        // wavefront free: words staged after the grids of levels 0..2, symbols at
-        // the end of the stage (clear of the level 1..2 parent lists).  Wavefronts
+        // wavefront free: words staged after the grids of levels 0..2, symbols in
+        // the parent-list area when they are read there, else at the end of the
+        // stage (clear of the level 1..2 parent lists).  Wavefronts
         // 0..G-1 decode the lane groups, wavefront G decodes levels 0..2 as soon
         // as every group is past their symbols, and the last wavefront, when it
         // is not G, parses the next task.
         constexpr uint32_t kLoGrid = 256;  // bytes of the level 0..2 grids
         const uint32_t G1 = ((1u << h.log2W) + 63u) / 64u;
         // (two or more lanes: a round writes whole bytes of symbol pairs)
-        const bool overlap = G1 < NT / 64 && h.log2W >= 1u && !sym_lds && !h.big && h.t >= 3 && h.t <= 5 &&
-                             kLoGrid + words_bytes <= u_at && sym_bytes + u_at + 48u <= stage_bytes;
+        const bool overlap = G1 < NT / 64 && h.log2W >= 1u && !h.big && h.t >= 3 && h.t <= 5 &&
+                             kLoGrid + words_bytes <= u_at && (sym_lds || sym_bytes + u_at + 48u <= stage_bytes);
         if (overlap) {
             const uint32_t wave = threadIdx.x >> 6;
             uint16_t* const wl = (uint16_t*)(stage + kLoGrid);
-            uint8_t* const nl = stage + ((stage_bytes - sym_bytes) & ~15u);
+            uint8_t* const nl = sym_lds ? nib : stage + ((stage_bytes - sym_bytes) & ~15u);
             if (threadIdx.x < 4) sh.prog[threadIdx.x] = 0;
             const uint32_t x0 = rans_stage_words<NT>(P, h, wl);
             __syncthreads();
@@ -1274,8 +1275,10 @@ __device__ __forceinline__ void decode_task(const Params& P, Shared& sh, uint16_
                 ah.done = true;
             }
             __syncthreads();
-            const uint32_t nw = ((h.nsym + 1u) / 2u + 3u) / 4u;
-            for (uint32_t q = threadIdx.x; q < nw; q += NT) ((uint32_t*)nib)[q] = ((const uint32_t*)nl)[q];
+            if (!sym_lds) {
+                const uint32_t nw = ((h.nsym + 1u) / 2u + 3u) / 4u;
+                for (uint32_t q = threadIdx.x; q < nw; q += NT) ((uint32_t*)nib)[q] = ((const uint32_t*)nl)[q];
+            }
             small_done = true;
         } else if (sym_lds && words_bytes <= nl_at) rans_decode_lds<NT>(P, sh, tab, stage, nib, nullptr);
         else if (!sym_lds && words_bytes + sym_bytes <= stage_bytes)
