@@ -605,6 +605,28 @@ public:
         std::vector<std::vector<ServeDone>> parts(T_), early(T_);
         std::vector<std::vector<uint64_t>> late(T_);  // parts completed in a shard's last step
         std::atomic<bool> stop{false};
+        // The trace is split once: thread c buckets the pairs of its contiguous
+        // range of requests by shard (local brick ids, per-request counts); after
+        // all threads have, shard w concatenates its buckets in request order.
+        struct Bucket {
+            std::vector<uint32_t> ids, count;  // count: pairs of each request of the range
+            std::vector<uint8_t> lods;
+        };
+        std::vector<std::vector<Bucket>> bucket(T_, std::vector<Bucket>(T_));
+        std::atomic<uint32_t> split_done{0};
+        auto split = [&](uint32_t c) {
+            const uint32_t r_lo = (uint32_t)((uint64_t)n_req * c / T_), r_hi = (uint32_t)((uint64_t)n_req * (c + 1) / T_);
+            std::vector<Bucket>& b = bucket[c];
+            for (auto& x : b) x.count.assign(r_hi - r_lo, 0u);
+            for (uint32_t r = r_lo; r < r_hi; ++r)
+                for (uint64_t j = starts[r]; j < starts[r + 1]; ++j) {
+                    Bucket& x = b[ids[j] % T_];
+                    x.ids.push_back(ids[j] / T_);
+                    x.lods.push_back(lods[j]);
+                    ++x.count[r - r_lo];
+                }
+            split_done.fetch_add(1);
+        };
         auto serve = [&](uint32_t w) {
             Scheduler<Backend>& s = *sh_[w];
             // this shard's pairs of every request, as local brick ids
@@ -615,14 +637,20 @@ public:
             const uint8_t* pl = lods;
             const uint64_t* ps = starts;
             if (T_ > 1) {
+                split(w);
+                // every thread is running (one per shard), so this wait ends
+                while (split_done.load() < T_) std::this_thread::yield();
+                size_t total = 0;
+                for (uint32_t c = 0; c < T_; ++c) total += bucket[c][w].ids.size();
+                li.reserve(total);
+                ll.reserve(total);
                 ls.assign(n_req + 1, 0);
-                for (uint32_t r = 0; r < n_req; ++r) {
-                    for (uint64_t j = starts[r]; j < starts[r + 1]; ++j)
-                        if (ids[j] % T_ == w) {
-                            li.push_back(ids[j] / T_);
-                            ll.push_back(lods[j]);
-                        }
-                    ls[r + 1] = li.size();
+                uint32_t r = 0;
+                for (uint32_t c = 0; c < T_; ++c) {
+                    const Bucket& x = bucket[c][w];
+                    li.insert(li.end(), x.ids.begin(), x.ids.end());
+                    ll.insert(ll.end(), x.lods.begin(), x.lods.end());
+                    for (uint32_t q = 0; q < (uint32_t)x.count.size(); ++q, ++r) ls[r + 1] = ls[r] + x.count[q];
                 }
                 pi = li.data();
                 pl = ll.data();
