@@ -907,12 +907,13 @@ __device__ __forceinline__ void level_passes(const Params& P, Shared& sh, const 
     if ((k_done != expected || carry != 0) && tid == 0) sh.err = 1u;
 }
 
-// Levels 0..min(t, 2) (at most 73 nodes) decoded by the calling wavefront
-// alone, with wave barriers; then the parent prefix of level 3 when the cube
-// has one, and the ADV count in sh.adv.
+// Levels 0..min(t, last) (last = 2: at most 73 nodes; 3: 585) decoded by the
+// calling wavefront alone, with wave barriers; then the parent prefix of the
+// next level when the cube has one, and the ADV count in sh.adv.
 template <typename V, bool BIG, bool LIST_LDS>
-__device__ __forceinline__ void small_levels(const Params& P, Shared& sh, const Store<V>& st, const uint8_t* nib) {
-    const uint32_t t = sh.h.t, tw = t < 2u ? t : 2u, lane = lane_id();
+__device__ __forceinline__ void small_levels(const Params& P, Shared& sh, const Store<V>& st, const uint8_t* nib,
+                                             uint32_t last) {
+    const uint32_t t = sh.h.t, tw = t < last ? t : last, lane = lane_id();
     uint32_t adv_done = 0, pbuf = 0;
     for (uint32_t i = 0; i <= tw; ++i) {
         uint32_t expected = 1;
@@ -947,19 +948,20 @@ __device__ __forceinline__ void small_levels(const Params& P, Shared& sh, const 
 }
 
 // Decode levels 0..t; on return all slots of level t are final unless sh.err.
-// Levels 0..2 are decoded by one wavefront (wavefront 0 here, unless `small_done`:
-// they were decoded during the rANS decode), the other wavefronts wait at the
-// work-group barrier that follows.  From level 3 on, all threads decode;
-// wavefront 0 computes the next level's parent prefix after a level's last
-// pass, before the barrier that ends it.
+// Levels 0..2 are decoded by one wavefront (wavefront 0 here; with `small_upto`
+// >= 0, levels 0..min(t, small_upto) were decoded during the rANS decode), the
+// other wavefronts wait at the work-group barrier that follows.  From then on,
+// all threads decode; wavefront 0 computes the next level's parent prefix after
+// a level's last pass, before the barrier that ends it.
 template <int NT, typename V, bool BIG, bool LIST_LDS>
 __device__ __forceinline__ void decode_levels(const Params& P, Shared& sh, const Store<V>& st, const uint8_t* nib,
-                                              Ahead& ah, bool small_done) {
+                                              Ahead& ah, int small_upto) {
     const uint32_t t = sh.h.t, wave = threadIdx.x >> 6;
-    const uint32_t tw = t < 2u ? t : 2u;  // last level of the single wavefront
-    if (!small_done) {
+    const uint32_t last = small_upto < 0 ? 2u : (uint32_t)small_upto;
+    const uint32_t tw = t < last ? t : last;  // last level of the single wavefront
+    if (small_upto < 0) {
         if (wave == 0) {
-            small_levels<V, BIG, LIST_LDS>(P, sh, st, nib);
+            small_levels<V, BIG, LIST_LDS>(P, sh, st, nib, 2u);
         } else if (threadIdx.x == NT - 64 && !ah.done) {
             parse_ahead(P, sh.hn, ah.jt);
             ah.done = true;
@@ -1183,11 +1185,11 @@ __device__ __forceinline__ Store<V> make_store(const Params& P, Shared& sh, uint
 
 template <int NT, typename V, bool BIG>
 __device__ __forceinline__ void run_levels(const Params& P, Shared& sh, uint16_t* slots_lds, uint8_t* scratch, const uint8_t* nib,
-                                           Ahead& ah, bool small_done) {
+                                           Ahead& ah, int small_upto) {
     const TaskHdr& h = sh.h;
     const Store<V> st = make_store<V, BIG>(P, sh, slots_lds, scratch);
-    if (!BIG && h.t <= 5) decode_levels<NT, V, BIG, true>(P, sh, st, nib, ah, small_done);
-    else decode_levels<NT, V, BIG, false>(P, sh, st, nib, ah, small_done);
+    if (!BIG && h.t <= 5) decode_levels<NT, V, BIG, true>(P, sh, st, nib, ah, small_upto);
+    else decode_levels<NT, V, BIG, false>(P, sh, st, nib, ah, small_upto);
     if (sh.err) return;
     // palette staging for the output pass (the parent list is no longer needed);
     // a cube of side <= 8 reads its few labels straight from the record
@@ -1215,7 +1217,8 @@ __device__ __forceinline__ void decode_task(const Params& P, Shared& sh, uint16_
     constexpr uint32_t kListMax4 = 1024;
     const bool sym_lds = h.t <= 4 && (h.nsym + 1u) / 2u + 4u <= kUBytes - kListMax4;
     uint8_t* const nib = sym_lds ? sh.U + kListMax4 : scratch + kScrSym;
-    bool tab_used = false, small_done = false;
+    bool tab_used = false;
+    int small_upto = -1;  // last level decoded during the rANS decode
     if (h.coder == kRaw4) {
         const uint32_t bytes = (h.nsym + 1u) / 2u, words = bytes / 4u;
         const uint32_t* src = (const uint32_t*)(P.vol + h.pay_off);
@@ -1243,17 +1246,18 @@ __device__ __forceinline__ void decode_task(const Params& P, Shared& sh, uint16_
         const uint32_t u_at = (uint32_t)(offsetof(Shared, U) - offsetof(Shared, G));
         const uint32_t nl_at = u_at + kListMax4;
         // Overlap, for a fast-path cube with a level 3 whose lane groups leave a
-        // wavefront free: words staged after the grids of levels 0..2, symbols in
+        // wavefront free: words staged after the grids of levels 0..3, symbols in
         // the parent-list area when they are read there, else at the end of the
-        // stage (clear of the level 1..2 parent lists).  Wavefronts
-        // 0..G-1 decode the lane groups, wavefront G decodes levels 0..2 as soon
-        // as every group is past their symbols, and the last wavefront, when it
-        // is not G, parses the next task.
-        constexpr uint32_t kLoGrid = 256;  // bytes of the level 0..2 grids
+        // stage (clear of the level 1..3 parent lists).  Wavefronts
+        // 0..G-1 decode the lane groups, wavefront G decodes levels 0..2 (0..3 for
+        // a cube with a level 5, whose rounds last long enough) as soon as every
+        // group is past their symbols, and the last wavefront, when it is not G,
+        // parses the next task.
+        constexpr uint32_t kLoGrid = 1280;  // bytes of the level 0..3 grids (1184), rounded up
         const uint32_t G1 = ((1u << h.log2W) + 63u) / 64u;
         // (two or more lanes: a round writes whole bytes of symbol pairs)
         const bool overlap = G1 < NT / 64 && h.log2W >= 1u && !h.big && h.t >= 3 && h.t <= 5 &&
-                             kLoGrid + words_bytes <= u_at && (sym_lds || sym_bytes + u_at + 48u <= stage_bytes);
+                             kLoGrid + words_bytes <= u_at && (sym_lds || sym_bytes + u_at + 160u <= stage_bytes);
         if (overlap) {
             const uint32_t wave = threadIdx.x >> 6;
             uint16_t* const wl = (uint16_t*)(stage + kLoGrid);
@@ -1261,7 +1265,8 @@ __device__ __forceinline__ void decode_task(const Params& P, Shared& sh, uint16_
             if (threadIdx.x < 4) sh.prog[threadIdx.x] = 0;
             const uint32_t x0 = rans_stage_words<NT>(P, h, wl);
             __syncthreads();
-            const uint32_t need = h.sym_end[2];
+            const uint32_t last = h.t >= 5 ? 3u : 2u;
+            const uint32_t need = h.sym_end[last];
             if (wave < G1) {
                 rans_rounds<NT>(P, sh, tab, wl, nl, x0, need ? need : 1u);
             } else if (wave == G1) {
@@ -1269,7 +1274,7 @@ __device__ __forceinline__ void decode_task(const Params& P, Shared& sh, uint16_
                 for (uint32_t g = 0; g < G1; ++g)
                     while (__hip_atomic_load(&sh.prog[g], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < need)
                         __builtin_amdgcn_s_sleep(1);
-                small_levels<uint16_t, false, true>(P, sh, make_store<uint16_t, false>(P, sh, slots_lds, scratch), nl);
+                small_levels<uint16_t, false, true>(P, sh, make_store<uint16_t, false>(P, sh, slots_lds, scratch), nl, last);
             } else if (threadIdx.x == NT - 64 && !ah.done) {
                 parse_ahead(P, sh.hn, ah.jt);
                 ah.done = true;
@@ -1279,7 +1284,7 @@ __device__ __forceinline__ void decode_task(const Params& P, Shared& sh, uint16_
                 const uint32_t nw = ((h.nsym + 1u) / 2u + 3u) / 4u;
                 for (uint32_t q = threadIdx.x; q < nw; q += NT) ((uint32_t*)nib)[q] = ((const uint32_t*)nl)[q];
             }
-            small_done = true;
+            small_upto = (int)last;
         } else if (sym_lds && words_bytes <= nl_at) rans_decode_lds<NT>(P, sh, tab, stage, nib, nullptr);
         else if (!sym_lds && words_bytes + sym_bytes <= stage_bytes)
             rans_decode_lds<NT>(P, sh, tab, stage, stage + words_bytes, nib);
@@ -1289,8 +1294,8 @@ __device__ __forceinline__ void decode_task(const Params& P, Shared& sh, uint16_
     // level 5 of a fast-path task overwrites the table
     const bool tab_lost = !h.big && h.t >= 5;
     if (!sh.err) {
-        if (h.big) run_levels<NT, uint32_t, true>(P, sh, slots_lds, scratch, nib, ah, small_done);
-        else run_levels<NT, uint16_t, false>(P, sh, slots_lds, scratch, nib, ah, small_done);
+        if (h.big) run_levels<NT, uint32_t, true>(P, sh, slots_lds, scratch, nib, ah, small_upto);
+        else run_levels<NT, uint16_t, false>(P, sh, slots_lds, scratch, nib, ah, small_upto);
     }
     __syncthreads();
     if (sh.err) {
