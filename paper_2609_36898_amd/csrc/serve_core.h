@@ -128,6 +128,9 @@ public:
                 break;
             }
             waiting_.pop_front();
+            // a full batch goes out at once when a stream is free, so the device
+            // works while a long admission run continues
+            if (queued_.size() >= max_batch_) launch_full(now);
         }
         for (int s = 0; s < (int)batches_.size() && !queued_.empty(); ++s)
             if (batches_[s].empty() && !be_.busy(s)) launch(s);
@@ -386,6 +389,14 @@ private:
         std::fill(tail_.begin(), tail_.end(), kNil);
         top_ = 0;
         ++st_.resets;
+    }
+
+    // launch full batches on the streams that are (or have just become) free
+    void launch_full(double now) {
+        for (int s = 0; s < (int)batches_.size() && queued_.size() >= max_batch_; ++s) {
+            if (!batches_[s].empty() && be_.poll(s)) retire(s, now);
+            if (batches_[s].empty() && !be_.busy(s)) launch(s);
+        }
     }
 
     void launch(int s) {
