@@ -23,9 +23,11 @@
 //                 the output pass then overwrites in place with labels.
 // A slot holds either a final palette index (top bit set) or a reference to
 // a same-level slot whose value it copies (a neighbour operation whose target
-// is decoded in the same pass).  Fast path: 16-bit slots, levels 0..5 in LDS.
-// Big path (palettes above 2^15 entries or more level-5 nodes than the LDS
-// share holds): 32-bit slots in a per-work-group global scratch area.
+// is decoded in the same pass).  Fast path: 16-bit slots, levels 0..5 in LDS;
+// a 32^3 cube at full resolution with more level-5 nodes than the LDS share
+// holds keeps its 16-bit level-5 slots in the work-group's scratch instead.
+// Big path (palettes above 2^15 entries, or a 64^3 cube whose level 5 does not
+// fit): 32-bit slots in a per-work-group global scratch area.
 //
 // A level's symbol segment is consumed in passes of one symbol per thread.
 // Per wavefront, ballots classify each symbol as an operation or a 4-bit
@@ -73,7 +75,7 @@ constexpr uint32_t kHdrWords = 2 + 7 + 4;
 
 struct TaskHdr {
     uint32_t hw[kHdrWords];  // the record's first words (parse_task)
-    uint32_t task, status, write_ok, coder, L, t, log2W, pc, big, pal_lds, nsym;
+    uint32_t task, status, write_ok, coder, L, t, log2W, pc, big, c5g, pal_lds, nsym;
     uint32_t sym_end[7];
     uint32_t gw[4], gstart[4];
     uint64_t out_off, pal_off, pay_off, states_off;
@@ -269,7 +271,10 @@ __device__ __forceinline__ void parse_task(const Params& P, uint32_t task, TaskH
     h.nsym = h.sym_end[t];
     // explicit nodes of level 5: at most one per symbol of its segment
     const uint32_t need5 = t >= 5 ? h.sym_end[5] - h.sym_end[4] : 0u;
-    h.big = pc > 32768u || need5 > P.cap16;
+    // a 32^3 cube at full resolution whose level 5 outgrows the LDS slot area
+    // keeps levels 0..4 in LDS and only its level-5 slots in scratch (c5g)
+    h.big = pc > 32768u || (need5 > P.cap16 && t != 5);
+    h.c5g = !h.big && need5 > P.cap16;
     h.pal_lds = (uint64_t)pc * lb <= kUBytes;
     // cache-paletted output: a palette beyond 2^I entries, or a 64^3 cube, has no packed form
     if (P.pal_bits && (t == 6 || (uint64_t)pc > (1ull << P.pal_bits))) {
@@ -1160,7 +1165,7 @@ __device__ __forceinline__ void write_output(const Params& P, Shared& sh, const 
 }
 
 // ------------------------------------------------------------------ a task
-template <typename V, bool BIG>
+template <typename V, bool BIG, bool C5G>
 __device__ __forceinline__ Store<V> make_store(const Params& P, Shared& sh, uint16_t* slots_lds, uint8_t* scratch) {
     const TaskHdr& h = sh.h;
     Store<V> st;
@@ -1178,16 +1183,16 @@ __device__ __forceinline__ Store<V> make_store(const Params& P, Shared& sh, uint
         st.c5 = (V*)(scratch + kScrComp);
     } else {
         st.full = (V*)sh.G;
-        st.c5 = (V*)slots_lds;
+        st.c5 = C5G ? (V*)(scratch + kScrComp) : (V*)slots_lds;
     }
     return st;
 }
 
-template <int NT, typename V, bool BIG>
+template <int NT, typename V, bool BIG, bool C5G>
 __device__ __forceinline__ void run_levels(const Params& P, Shared& sh, uint16_t* slots_lds, uint8_t* scratch, const uint8_t* nib,
                                            Ahead& ah, int small_upto) {
     const TaskHdr& h = sh.h;
-    const Store<V> st = make_store<V, BIG>(P, sh, slots_lds, scratch);
+    const Store<V> st = make_store<V, BIG, C5G>(P, sh, slots_lds, scratch);
     if (!BIG && h.t <= 5) decode_levels<NT, V, BIG, true>(P, sh, st, nib, ah, small_upto);
     else decode_levels<NT, V, BIG, false>(P, sh, st, nib, ah, small_upto);
     if (sh.err) return;
@@ -1274,7 +1279,7 @@ __device__ __forceinline__ void decode_task(const Params& P, Shared& sh, uint16_
                 for (uint32_t g = 0; g < G1; ++g)
                     while (__hip_atomic_load(&sh.prog[g], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < need)
                         __builtin_amdgcn_s_sleep(1);
-                small_levels<uint16_t, false, true>(P, sh, make_store<uint16_t, false>(P, sh, slots_lds, scratch), nl, last);
+                small_levels<uint16_t, false, true>(P, sh, make_store<uint16_t, false, false>(P, sh, slots_lds, scratch), nl, last);
             } else if (threadIdx.x == NT - 64 && !ah.done) {
                 parse_ahead(P, sh.hn, ah.jt);
                 ah.done = true;
@@ -1292,10 +1297,11 @@ __device__ __forceinline__ void decode_task(const Params& P, Shared& sh, uint16_
         __syncthreads();
     }
     // level 5 of a fast-path task overwrites the table
-    const bool tab_lost = !h.big && h.t >= 5;
+    const bool tab_lost = !h.big && !h.c5g && h.t >= 5;
     if (!sh.err) {
-        if (h.big) run_levels<NT, uint32_t, true>(P, sh, slots_lds, scratch, nib, ah, small_upto);
-        else run_levels<NT, uint16_t, false>(P, sh, slots_lds, scratch, nib, ah, small_upto);
+        if (h.big) run_levels<NT, uint32_t, true, false>(P, sh, slots_lds, scratch, nib, ah, small_upto);
+        else if (h.c5g) run_levels<NT, uint16_t, false, true>(P, sh, slots_lds, scratch, nib, ah, small_upto);
+        else run_levels<NT, uint16_t, false, false>(P, sh, slots_lds, scratch, nib, ah, small_upto);
     }
     __syncthreads();
     if (sh.err) {
