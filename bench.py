@@ -188,7 +188,11 @@ def measure(wl: Workload, args, dev):
     stream = torch.cuda.current_stream(dev)
     plan = P.csgv_plan(dv.info, n)
     tune = None
-    if not args.no_tune:
+    if args.shape:
+        wg, slots, per_cu = (int(v) for v in args.shape.split(","))
+        plan.set_opts(wg_size=wg, lds_slots=slots, wgs_per_cu=per_cu)
+        tune = {"fixed_shape": args.shape}
+    elif not args.no_tune:
         rep = plan.autotune(stream, dv.tensor, d_ids, d_lods, d_offs, n, out, total, status,
                             cache_path=args.tune_cache)
         tune = {"from_cache": bool(rep.from_cache), "tried": int(rep.tried), "best_kernel_ms": round(rep.best_ms, 4),
@@ -714,6 +718,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain one-launch-per-brick legs")
     ap.add_argument("--no-tune", action="store_true", help="default launch shape instead of the autotuner")
+    ap.add_argument("--shape", default=None, metavar="WG,SLOTS,WGS_PER_CU",
+                    help="fixed launch shape of the batched legs instead of the autotuner (profiling runs)")
     ap.add_argument("--no-paletted", action="store_true", help="skip the cache-paletted leg of neurite1024")
     ap.add_argument("--ablation", action="store_true",
                     help="operation-set ablation (compressed size and decode GVoxel/s per op prefix) instead")
