@@ -358,6 +358,74 @@ const char* csgv_server_last_error(void);
 void csgv_server_destroy(csgv_server* server);
 
 /*
+ * Device-resident cache stages (Methods > "GPU rendering pipeline": the
+ * request, provision and assign stages that run before decompression;
+ * Methods > "Memory management": per-LOD free stacks of released slots and an
+ * atomic cache top).  A batch of (brick, LOD) requests becomes decode tasks on
+ * the device, with no host round trip:
+ *
+ *   csgv_dcache_request(c, s, d_ids, d_lods, n, d_task_ids, d_slot, d_state);
+ *   csgv_plan_launch(plan, s, d_container, d_task_ids, d_lods, d_slot, n,
+ *                    d_cache, cache_elements, d_status);
+ *
+ * The cache is a flat array of cache_elements labels owned by the caller; a
+ * pair of side exponent t = log2(brick side) - lod occupies 8^t elements at
+ * its slot (element offset).  The library owns a device slot table (8 bytes
+ * per brick and LOD), free stacks of stack_cap entries per size class t
+ * (0 = 2^20; with one brick side a class is one LOD, as in the paper) and the
+ * cache top, about 8 * (8 * n_bricks + 7 * stack_cap) bytes of device memory.
+ * The brick side of a pair is read from its record in d_container, which must
+ * stay valid for the cache's lifetime.
+ *
+ * csgv_dcache_request, one thread per request (device arrays of n entries):
+ *   d_state[i]    CSGV_DC_NEW: the pair was absent and got a slot; request i
+ *                 is its decode task (d_task_ids[i] = its brick id).
+ *                 CSGV_DC_HIT: resident already (possibly placed by another
+ *                 request of the same call).  CSGV_DC_JOINED: another request
+ *                 of the same call provisions it.  CSGV_DC_FULL: absent, and
+ *                 neither the free stack of its class nor the cache top had
+ *                 room.  CSGV_DC_INVALID: no such brick, a LOD beyond its
+ *                 side, or an unusable record.
+ *   d_slot[i]     element offset of the pair's slot (NEW, HIT, JOINED), else
+ *                 0xFFFFFFFFFFFFFFFF.
+ *   d_task_ids[i] the brick id for NEW, else 0xFFFFFFFF, which every decode
+ *                 entry point rejects (CSGV_TASK_INVALID) before it touches
+ *                 the output; so d_task_ids / d_lods / d_slot are the decode's
+ *                 task arrays as they stand.
+ *   Exactly one request per absent pair is NEW unless the cache is full; which
+ *   one, and which slot it gets, depends on the order the device runs them.
+ * csgv_dcache_free releases pairs (duplicates and absent pairs are ignored):
+ *   their slots go onto the free stack of their class for reuse by later
+ *   requests of the same class (a full stack drops the slot until a reset).
+ * csgv_dcache_reset empties the cache (all pairs absent, top 0, stacks empty).
+ * csgv_dcache_query copies the top (elements) and the 7 stack counts to the
+ *   host and synchronizes the stream.
+ * Calls are stream-ordered: a request, decode and free issued on one stream
+ * run in that order; calls on one cache from several streams at once race.
+ * Errors: CSGV_EINVAL for null arguments (nothing enqueued), CSGV_EHIP when a
+ * launch fails, CSGV_ENOMEM when the state does not fit; the message is in
+ * csgv_dcache_last_error.
+ */
+enum {
+    CSGV_DC_NEW = 0,
+    CSGV_DC_HIT = 1,
+    CSGV_DC_JOINED = 2,
+    CSGV_DC_FULL = 3,
+    CSGV_DC_INVALID = 4
+};
+typedef struct csgv_dcache csgv_dcache;
+csgv_status csgv_dcache_create(const csgv_volume_info* vol, const void* d_container, uint64_t cache_elements,
+                               uint32_t stack_cap, hipStream_t stream, csgv_dcache** out);
+csgv_status csgv_dcache_request(csgv_dcache* cache, hipStream_t stream, const uint32_t* d_ids, const uint8_t* d_lods,
+                                uint32_t n, uint32_t* d_task_ids, uint64_t* d_slot, uint32_t* d_state);
+csgv_status csgv_dcache_free(csgv_dcache* cache, hipStream_t stream, const uint32_t* d_ids, const uint8_t* d_lods,
+                             uint32_t n);
+csgv_status csgv_dcache_reset(csgv_dcache* cache, hipStream_t stream);
+csgv_status csgv_dcache_query(csgv_dcache* cache, hipStream_t stream, uint64_t* h_top, int32_t* h_counts);
+const char* csgv_dcache_last_error(void);
+void csgv_dcache_destroy(csgv_dcache* cache);
+
+/*
  * CPU encoder (host only, multi-threaded over bricks; Methods > "Compressed
  * segmentation volumes": one operation per explicit node, coarse to fine,
  * copy from parent or neighbour when possible, else from the palette).

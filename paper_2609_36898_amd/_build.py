@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcsgv.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["decode_kernel.hip", "csgv_api.hip", "serve.hip", "encoder.cpp"]
+SOURCES = ["decode_kernel.hip", "csgv_api.hip", "serve.hip", "dcache.hip", "encoder.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed fp32 instructions stay off (no float math here, but keep the build uniform)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -435,3 +435,65 @@ class csgv_server:
             self.destroy()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- device-resident cache stages
+DC_NEW, DC_HIT, DC_JOINED, DC_FULL, DC_INVALID = 0, 1, 2, 3, 4
+DC_NO_TASK = 0xFFFFFFFF
+DC_NO_SLOT = 0xFFFFFFFFFFFFFFFF
+
+_lib.csgv_dcache_create.argtypes = [ctypes.POINTER(VolumeInfo), _P, _U64, _U32, _P, ctypes.POINTER(_P)]
+_lib.csgv_dcache_request.argtypes = [_P, _P, _P, _P, _U32, _P, _P, _P]
+_lib.csgv_dcache_free.argtypes = [_P, _P, _P, _P, _U32]
+_lib.csgv_dcache_reset.argtypes = [_P, _P]
+_lib.csgv_dcache_query.argtypes = [_P, _P, _P, _P]
+_lib.csgv_dcache_last_error.restype = ctypes.c_char_p
+_lib.csgv_dcache_destroy.argtypes = [_P]
+EXPORTED += ["csgv_dcache_create", "csgv_dcache_request", "csgv_dcache_free", "csgv_dcache_reset",
+             "csgv_dcache_query", "csgv_dcache_last_error", "csgv_dcache_destroy"]
+
+
+def _dcheck(rc: int, where: str):
+    if rc != CSGV_OK:
+        msg = _lib.csgv_dcache_last_error().decode(errors="replace")
+        err = CsgvError(rc, where)
+        err.args = ("%s failed (%d): %s" % (where, rc, msg),)
+        raise err
+
+
+class csgv_dcache:
+    """Owner of a csgv_dcache* (slot table, free stacks and cache top on the device)."""
+
+    def __init__(self, vol: VolumeInfo, d_container, cache_elements: int, stack_cap: int = 0, stream=None):
+        self._h = ctypes.c_void_p()
+        _dcheck(_lib.csgv_dcache_create(ctypes.byref(vol), _ptr(d_container), cache_elements, stack_cap,
+                                        _stream(stream), ctypes.byref(self._h)), "csgv_dcache_create")
+
+    def request(self, stream, d_ids, d_lods, n: int, d_task_ids, d_slot, d_state):
+        _dcheck(_lib.csgv_dcache_request(self._h, _stream(stream), _ptr(d_ids), _ptr(d_lods), n, _ptr(d_task_ids),
+                                         _ptr(d_slot), _ptr(d_state)), "csgv_dcache_request")
+
+    def free(self, stream, d_ids, d_lods, n: int):
+        _dcheck(_lib.csgv_dcache_free(self._h, _stream(stream), _ptr(d_ids), _ptr(d_lods), n), "csgv_dcache_free")
+
+    def reset(self, stream=None):
+        _dcheck(_lib.csgv_dcache_reset(self._h, _stream(stream)), "csgv_dcache_reset")
+
+    def query(self, stream=None):
+        """(top in elements, free-stack counts per size class); synchronizes the stream."""
+        top = np.zeros(1, np.uint64)
+        counts = np.zeros(7, np.int32)
+        _dcheck(_lib.csgv_dcache_query(self._h, _stream(stream), top.ctypes.data, counts.ctypes.data),
+                "csgv_dcache_query")
+        return int(top[0]), counts
+
+    def destroy(self):
+        if self._h:
+            _lib.csgv_dcache_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -1,0 +1,274 @@
+// Device-resident brick cache stages: request, provision and assign run on the
+// GPU, so a batch of (brick, LOD) requests turns into decode tasks with no host
+// round trip (Methods > GPU rendering pipeline, the request / provision /
+// assign stages ahead of decompression; Methods > Memory management, per-LOD
+// free stacks and a cache top pointer).
+//
+// State in device memory (one allocation):
+//   slot_of[id * 8 + lod]  element offset of a resident pair, kEmpty, or kPending
+//                          while the request kernel that claimed it runs
+//   stack[c][k], count[c]  free stacks of released slots per size class
+//                          c = log2(side) - lod (a slot holds 8^c elements);
+//                          with one brick side this is the paper's per-LOD stack
+//   top                    elements handed out at the cache top so far
+//
+// Request kernel, one thread per request:
+//   1. validate the pair against the brick's record header (side exponent);
+//   2. claim the pair: CAS kEmpty -> kPending.  The winner provisions a slot:
+//      pop its class's free stack, else advance the cache top atomically; when
+//      neither has room the claim is undone (pair stays absent, state FULL);
+//   3. assign: the winner publishes the slot and becomes a decode task; every
+//      other request of the pair is a hit (slot already set) or joins the
+//      winner and takes its slot in the resolve kernel that follows.
+// Requests that are not decode tasks get brick id 0xFFFFFFFF, which the decoder
+// rejects before touching the output, so the decode launch takes the request
+// arrays as they are, with the request count the host already knows.
+//
+// Free-stack pops run only in the request kernel and pushes only in the free
+// kernel, so neither kernel sees both.  A pop decrements the count and owns
+// entry count-1 when the old count was positive; an unlucky pop adds its 1
+// back.  The first failing pop happens only once every entry is taken, and no
+// pop after it can succeed, so successful pops take distinct entries.  The top
+// works the same way: a failed advance is subtracted again, and while one is
+// outstanding the top exceeds the capacity, so no advance can succeed then.
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "csgv.h"
+#include "csgv_format.h"
+
+namespace csgv {
+namespace {
+
+constexpr uint64_t kEmpty = ~0ull;
+constexpr uint64_t kPending = ~0ull - 1;
+constexpr uint32_t kClasses = kMaxLog2b + 1;
+constexpr uint32_t kNoTask = 0xFFFFFFFFu;
+
+struct DcState {
+    unsigned long long* slot_of;  // n_bricks * 8
+    unsigned long long* stack;    // kClasses * stack_cap
+    int* count;                   // kClasses
+    unsigned long long* top;      // 1
+    uint32_t n_bricks;
+    uint32_t stack_cap;
+    uint64_t cache_elems;
+    const uint8_t* vol;
+    uint64_t vol_bytes;
+    uint64_t off_pos;
+};
+
+thread_local std::string g_dc_error;
+
+csgv_status dc_fail(csgv_status s, const std::string& m) {
+    g_dc_error = m;
+    return s;
+}
+
+// side exponent of brick id's record, or 0xFF when the record is unusable
+__device__ uint32_t record_log2b(const DcState& S, uint32_t id) {
+    const uint64_t* offs = (const uint64_t*)(S.vol + S.off_pos);
+    const uint64_t a = offs[id], b = offs[id + 1];
+    if (a > b || b > S.vol_bytes || (a & 7) || b - a < 8) return 0xFFu;
+    const uint32_t L = S.vol[a + 1];
+    return (L >= 1 && L <= kMaxLog2b) ? L : 0xFFu;
+}
+
+__global__ void dc_fill_kernel(unsigned long long* p, uint64_t n, unsigned long long v) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void dc_zero_counters_kernel(int* count, unsigned long long* top) {
+    if (threadIdx.x < kClasses) count[threadIdx.x] = 0;
+    if (threadIdx.x == 0) *top = 0;
+}
+
+__global__ void __launch_bounds__(256) dc_request_kernel(DcState S, const uint32_t* ids, const uint8_t* lods,
+                                                         uint32_t n, uint32_t* task_ids, uint64_t* slot,
+                                                         uint32_t* state) {
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t id = ids[i], lod = lods[i];
+    task_ids[i] = kNoTask;
+    slot[i] = kEmpty;
+    const uint32_t L = id < S.n_bricks ? record_log2b(S, id) : 0xFFu;
+    if (L == 0xFFu || lod > L) {
+        state[i] = CSGV_DC_INVALID;
+        return;
+    }
+    unsigned long long* key = S.slot_of + (uint64_t)id * 8 + lod;
+    const unsigned long long old = atomicCAS(key, kEmpty, kPending);
+    if (old == kPending) {  // another request of this launch provisions the pair
+        state[i] = CSGV_DC_JOINED;
+        return;
+    }
+    if (old != kEmpty) {  // resident
+        slot[i] = old;
+        state[i] = CSGV_DC_HIT;
+        return;
+    }
+    const uint32_t c = L - lod;
+    const unsigned long long units = 1ull << (3 * c);
+    unsigned long long off = kEmpty;
+    const int k = atomicSub(&S.count[c], 1);
+    if (k > 0) {
+        off = S.stack[(uint64_t)c * S.stack_cap + (uint32_t)(k - 1)];
+    } else {
+        atomicAdd(&S.count[c], 1);
+        const unsigned long long t = atomicAdd(S.top, units);
+        if (t <= S.cache_elems && units <= S.cache_elems - t)
+            off = t;
+        else
+            atomicSub(S.top, units);
+    }
+    if (off == kEmpty) {
+        atomicExch(key, kEmpty);
+        state[i] = CSGV_DC_FULL;
+        return;
+    }
+    atomicExch(key, off);
+    task_ids[i] = id;
+    slot[i] = off;
+    state[i] = CSGV_DC_NEW;
+}
+
+// joined requests take their winner's slot (or FULL when the winner found no room)
+__global__ void __launch_bounds__(256) dc_resolve_kernel(DcState S, const uint32_t* ids, const uint8_t* lods,
+                                                         uint32_t n, uint64_t* slot, uint32_t* state) {
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n || state[i] != CSGV_DC_JOINED) return;
+    const unsigned long long v = S.slot_of[(uint64_t)ids[i] * 8 + lods[i]];
+    if (v == kEmpty || v == kPending)
+        state[i] = CSGV_DC_FULL;
+    else
+        slot[i] = v;
+}
+
+__global__ void __launch_bounds__(256) dc_free_kernel(DcState S, const uint32_t* ids, const uint8_t* lods,
+                                                      uint32_t n) {
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t id = ids[i], lod = lods[i];
+    if (id >= S.n_bricks || lod > kMaxLog2b) return;
+    const unsigned long long old = atomicExch(S.slot_of + (uint64_t)id * 8 + lod, kEmpty);
+    if (old == kEmpty || old == kPending) return;
+    const uint32_t L = record_log2b(S, id);
+    if (L == 0xFFu || lod > L) return;  // cannot happen for a pair the request kernel placed
+    const uint32_t c = L - lod;
+    const int k = atomicAdd(&S.count[c], 1);
+    if ((uint32_t)k < S.stack_cap)
+        S.stack[(uint64_t)c * S.stack_cap + (uint32_t)k] = old;
+    else
+        atomicSub(&S.count[c], 1);  // stack full: the slot is not reused until a reset
+}
+
+}  // namespace
+}  // namespace csgv
+
+using namespace csgv;
+
+struct csgv_dcache {
+    DcState S;
+    void* mem = nullptr;
+    int device = 0;
+};
+
+extern "C" {
+
+const char* csgv_dcache_last_error(void) { return g_dc_error.c_str(); }
+
+csgv_status csgv_dcache_reset(csgv_dcache* c, hipStream_t stream) {
+    if (!c) return dc_fail(CSGV_EINVAL, "csgv_dcache_reset: null cache");
+    const uint64_t n = (uint64_t)c->S.n_bricks * 8;
+    hipLaunchKernelGGL(dc_fill_kernel, dim3((uint32_t)std::min<uint64_t>((n + 255) / 256, 4096)), dim3(256), 0, stream,
+                       c->S.slot_of, n, kEmpty);
+    hipLaunchKernelGGL(dc_zero_counters_kernel, dim3(1), dim3(64), 0, stream, c->S.count, c->S.top);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return dc_fail(CSGV_EHIP, std::string("csgv_dcache_reset: ") + hipGetErrorString(e));
+    return CSGV_OK;
+}
+
+csgv_status csgv_dcache_create(const csgv_volume_info* vol, const void* d_container, uint64_t cache_elements,
+                               uint32_t stack_cap, hipStream_t stream, csgv_dcache** out) {
+    if (!vol || !d_container || !out) return dc_fail(CSGV_EINVAL, "csgv_dcache_create: null argument");
+    *out = nullptr;
+    if (vol->n_bricks == 0 || cache_elements == 0)
+        return dc_fail(CSGV_EINVAL, "csgv_dcache_create: empty volume or cache");
+    if (stack_cap == 0) stack_cap = 1u << 20;
+    if (stack_cap > (1u << 30)) return dc_fail(CSGV_EINVAL, "csgv_dcache_create: stack_cap above 2^30");
+    const uint64_t n_keys = (uint64_t)vol->n_bricks * 8;
+    const uint64_t bytes = 8 * n_keys + 8ull * kClasses * stack_cap + 8 + 4 * kClasses + 256;
+    csgv_dcache* c = new csgv_dcache();
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = hipMalloc(&c->mem, bytes);
+    if (e != hipSuccess) {
+        delete c;
+        return dc_fail(e == hipErrorOutOfMemory ? CSGV_ENOMEM : CSGV_EHIP,
+                       std::string("csgv_dcache_create: ") + hipGetErrorString(e));
+    }
+    uint8_t* p = (uint8_t*)c->mem;
+    c->S.slot_of = (unsigned long long*)p;
+    c->S.stack = (unsigned long long*)(p + 8 * n_keys);
+    c->S.top = (unsigned long long*)(p + 8 * n_keys + 8ull * kClasses * stack_cap);
+    c->S.count = (int*)(p + 8 * n_keys + 8ull * kClasses * stack_cap + 8);
+    c->S.n_bricks = vol->n_bricks;
+    c->S.stack_cap = stack_cap;
+    c->S.cache_elems = cache_elements;
+    c->S.vol = (const uint8_t*)d_container;
+    c->S.vol_bytes = vol->total_bytes;
+    c->S.off_pos = vol->offsets_pos;
+    const csgv_status s = csgv_dcache_reset(c, stream);
+    if (s != CSGV_OK) {
+        (void)hipFree(c->mem);
+        delete c;
+        return s;
+    }
+    *out = c;
+    return CSGV_OK;
+}
+
+void csgv_dcache_destroy(csgv_dcache* c) {
+    if (!c) return;
+    (void)hipDeviceSynchronize();
+    (void)hipFree(c->mem);
+    delete c;
+}
+
+csgv_status csgv_dcache_request(csgv_dcache* c, hipStream_t stream, const uint32_t* d_ids, const uint8_t* d_lods,
+                                uint32_t n, uint32_t* d_task_ids, uint64_t* d_slot, uint32_t* d_state) {
+    if (!c) return dc_fail(CSGV_EINVAL, "csgv_dcache_request: null cache");
+    if (n == 0) return CSGV_OK;
+    if (!d_ids || !d_lods || !d_task_ids || !d_slot || !d_state)
+        return dc_fail(CSGV_EINVAL, "csgv_dcache_request: null array");
+    const dim3 grid((n + 255) / 256);
+    hipLaunchKernelGGL(dc_request_kernel, grid, dim3(256), 0, stream, c->S, d_ids, d_lods, n, d_task_ids, d_slot,
+                       d_state);
+    hipLaunchKernelGGL(dc_resolve_kernel, grid, dim3(256), 0, stream, c->S, d_ids, d_lods, n, d_slot, d_state);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return dc_fail(CSGV_EHIP, std::string("csgv_dcache_request: ") + hipGetErrorString(e));
+    return CSGV_OK;
+}
+
+csgv_status csgv_dcache_free(csgv_dcache* c, hipStream_t stream, const uint32_t* d_ids, const uint8_t* d_lods,
+                             uint32_t n) {
+    if (!c) return dc_fail(CSGV_EINVAL, "csgv_dcache_free: null cache");
+    if (n == 0) return CSGV_OK;
+    if (!d_ids || !d_lods) return dc_fail(CSGV_EINVAL, "csgv_dcache_free: null array");
+    hipLaunchKernelGGL(dc_free_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, c->S, d_ids, d_lods, n);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return dc_fail(CSGV_EHIP, std::string("csgv_dcache_free: ") + hipGetErrorString(e));
+    return CSGV_OK;
+}
+
+csgv_status csgv_dcache_query(csgv_dcache* c, hipStream_t stream, uint64_t* h_top, int32_t* h_counts) {
+    if (!c || !h_top || !h_counts) return dc_fail(CSGV_EINVAL, "csgv_dcache_query: null argument");
+    hipError_t e = hipMemcpyAsync(h_top, c->S.top, 8, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(h_counts, c->S.count, 4 * kClasses, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return dc_fail(CSGV_EHIP, std::string("csgv_dcache_query: ") + hipGetErrorString(e));
+    return CSGV_OK;
+}
+
+}  // extern "C"

@@ -173,3 +173,17 @@ def test_legacy_back_reference_limit(P):
             assert md > 16 and len(pal) == len(set(pal.tolist()))
         out, st = oracle.decode_tasks(c, [0], [0], [0], 4096, 4)
         assert st[0] == 0 and np.array_equal(out, brick.reshape(-1))
+
+
+def test_dcache_rejects_null_arguments_synchronously(P):
+    c = P.encode_volume(synth.voronoi_u32(64, 20, seed=1), 5)
+    info = P.csgv_volume_parse(c)
+    with pytest.raises(P.CsgvError) as e:
+        P.csgv.csgv_dcache(info, None, 1 << 20, stream=0)
+    assert e.value.code == P.csgv.CSGV_EINVAL
+    for rc in (P.csgv._lib.csgv_dcache_request(None, None, None, None, 4, None, None, None),
+               P.csgv._lib.csgv_dcache_free(None, None, None, None, 4),
+               P.csgv._lib.csgv_dcache_reset(None, None),
+               P.csgv._lib.csgv_dcache_query(None, None, None, None)):
+        assert rc == P.csgv.CSGV_EINVAL
+    assert b"null" in P.csgv._lib.csgv_dcache_last_error()
