@@ -460,6 +460,8 @@ def measure_served(wl: Workload, args, dev):
     want, wst = oracle.decode_tasks(wl.container, c_ids, c_lods, offs, total, 4, nthreads=cpu_threads())
     exact = exact and bool((wst == 0).all()) and bool(np.array_equal(np.concatenate(c_got), want))
     _log("%s: %d pinned requests (%d pairs) bit-exact vs oracle: %s" % (wl.name, len(check), len(c_ids), exact))
+    staged = None if args.no_dcache else device_staged(P, dv, cache, cache_elems, wl.container, ids, lods, starts, nw,
+                                                        args.dcache_chunk, args.dcache_keep)
     del cache, dv
     torch.cuda.empty_cache()
 
@@ -484,13 +486,115 @@ def measure_served(wl: Workload, args, dev):
                      "note": "over the saturation run: sum of algorithmic bytes / sum of decode-kernel times "
                              "(launches of several shards overlap); traffic = the profiled process's HBM bytes "
                              "over all decode dispatches / its algorithmic bytes, times alg_bytes_per_launch"},
-        "served": {"saturation": sat, **loads, "checked_requests": len(check), "checked_pairs": int(len(c_ids))},
-        "bit_exact": exact and sat["all_ok"] and all(v["all_ok"] for v in loads.values()),
+        "served": {"saturation": sat, **loads, "checked_requests": len(check), "checked_pairs": int(len(c_ids)),
+                   "device_staged": staged},
+        "bit_exact": exact and sat["all_ok"] and all(v["all_ok"] for v in loads.values())
+        and (staged is None or staged["bit_exact"]),
         "shape": {"wg_size": "default", "sort_tasks": "default"},
         "autotune": None,
     }
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline_served(wl, m_ids, m_lods, m_starts)
+    return res
+
+
+def device_staged(P, dv, cache, cache_elems, container, ids, lods, starts, n_warm, chunk_pairs, keep=16):
+    """The served trace with the cache stages on the device: whole requests
+    concatenated into chunks of at most chunk_pairs pairs; per chunk one
+    request/provision/assign call, one decode launch over the chunk's request
+    arrays (non-tasks are rejected by the decoder), then the release of every
+    pair whose last use was `keep` chunks ago (the no-longer-requested pairs go
+    onto the free stacks).  Every chunk is enqueued on one stream up front: no
+    host round trip.  Saturation only (all requests at t = 0); the warm-up
+    requests run first, untimed.  Bit-exactness: the last chunk's pairs, which
+    are still resident at the end, against the CPU oracle."""
+    import torch
+    import oracle
+    dev = cache.device
+    n_req = len(starts) - 1
+    sizes = np.diff(starts.astype(np.int64))
+    bounds, acc = [0], 0
+    for r in range(n_req):
+        if (acc + sizes[r] > chunk_pairs and acc > 0) or r == n_warm:
+            bounds.append(r)
+            acc = 0
+        acc += int(sizes[r])
+    bounds.append(n_req)
+    pb = [int(starts[b]) for b in bounds]  # pair boundaries of the chunks
+    n_chunks = len(bounds) - 1
+    first_measured = bounds.index(n_warm)
+    # release schedule: a pair used in chunk c and not again within `keep` chunks is freed after chunk c + keep
+    chunk_of = np.repeat(np.arange(n_chunks), np.diff(pb))
+    key = ids.astype(np.int64) * 8 + lods.astype(np.int64)
+    kc = np.unique(key * n_chunks + chunk_of)
+    k, c = kc // n_chunks, kc % n_chunks
+    nxt = np.full(len(kc), 1 << 40, np.int64)
+    same = k[1:] == k[:-1]
+    nxt[:-1][same] = c[1:][same]
+    rel = (nxt - c > keep) & (c + keep < n_chunks)
+    rk, rat = k[rel], c[rel] + keep
+    order = np.argsort(rat, kind="stable")
+    rk, rat = rk[order], rat[order]
+    rel_b = np.searchsorted(rat, np.arange(n_chunks + 1))
+    d_rel_ids = torch.from_numpy((rk // 8).astype(np.uint32).view(np.int32)).to(dev)
+    d_rel_lods = torch.from_numpy((rk % 8).astype(np.uint8)).to(dev)
+
+    n = int(starts[-1])
+    d_ids = torch.from_numpy(ids.astype(np.uint32).view(np.int32)).to(dev)
+    d_lods = torch.from_numpy(lods.astype(np.uint8)).to(dev)
+    task = torch.empty(n, dtype=torch.int32, device=dev)
+    slot = torch.empty(n, dtype=torch.int64, device=dev)
+    state = torch.empty(n, dtype=torch.int32, device=dev)
+    status = torch.empty(n, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    dc = P.csgv.csgv_dcache(dv.info, dv.tensor, cache_elems, stream=stream)
+    plan = P.csgv_plan(dv.info, max(int(np.diff(pb).max()), 1))
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for ch in range(n_chunks):
+        if ch == first_measured:
+            ev0.record(stream)
+        a, b = pb[ch], pb[ch + 1]
+        if b > a:
+            dc.request(stream, d_ids[a:], d_lods[a:], b - a, task[a:], slot[a:], state[a:])
+            plan.launch(stream, dv.tensor, task[a:], d_lods[a:], slot[a:], b - a, cache, cache_elems, status[a:])
+        r0, r1 = int(rel_b[ch]), int(rel_b[ch + 1])
+        if r1 > r0:
+            dc.free(stream, d_rel_ids[r0:], d_rel_lods[r0:], r1 - r0)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    host_s = time.time() - t0
+    secs = ev0.elapsed_time(ev1) * 1e-3
+    st = state.cpu().numpy()
+    ts = status.cpu().numpy()
+    sl = slot.cpu().numpy().view(np.uint64)
+    m0 = pb[first_measured]
+    new = st == 0
+    units = np.int64(1) << (3 * (5 - lods.astype(np.int64)))
+    ok = bool((ts[new] == 0).all())
+    full = int((st[m0:] == 3).sum())
+    # the last chunk's pairs against the oracle (a bounded sample)
+    a = pb[-2]
+    pick = np.arange(a, n)[:512]
+    host = [cache[int(sl[i]):int(sl[i]) + int(units[i])].cpu().numpy().view(np.uint32) for i in pick
+            if st[i] in (0, 1, 2)]
+    pids, plods = ids[pick][np.isin(st[pick], (0, 1, 2))], lods[pick][np.isin(st[pick], (0, 1, 2))]
+    offs, total = P.dense_offsets(np.full(len(pids), 5, np.uint8), plods)
+    want, wst = oracle.decode_tasks(container, pids, plods, offs, total, 4, nthreads=cpu_threads())
+    exact = ok and bool((wst == 0).all()) and bool(np.array_equal(np.concatenate(host), want)) if len(host) else ok
+    top, _ = dc.query(stream)
+    dc.destroy()
+    n_meas = n_req - n_warm
+    res = {"requests": n_meas, "chunks": n_chunks - first_measured, "max_chunk_pairs": chunk_pairs,
+           "release_after_chunks": keep, "seconds": round(secs, 4), "requests_per_s": round(n_meas / secs, 2),
+           "decoded_gvoxel_s": round(float(units[m0:][new[m0:]].sum()) / secs / 1e9, 3),
+           "served_gvoxel_s": round(float(units[m0:].sum()) / secs / 1e9, 3),
+           "hit_fraction": round(float((~new[m0:]).sum() - full) / max(n - m0, 1), 4),
+           "full_pairs": full, "cache_top_elements": top, "host_enqueue_s": round(host_s, 3),
+           "checked_pairs": int(len(pids)), "bit_exact": exact}
+    _log("device-staged: %.0f req/s, %.2f GVoxel/s decoded, %d chunks, hit fraction %.3f, full %d, exact %s" % (
+        res["requests_per_s"], res["decoded_gvoxel_s"], res["chunks"], res["hit_fraction"], full, exact))
     return res
 
 
@@ -731,6 +835,10 @@ def main():
     ap.add_argument("--serve-streams", type=int, default=2, help="HIP streams per cache shard")
     ap.add_argument("--serve-shards", type=int, default=16, help="cache shards (host threads) of the server")
     ap.add_argument("--serve-batch", type=int, default=16384, help="tasks per served batch (per shard stream)")
+    ap.add_argument("--no-dcache", action="store_true", help="skip the device-staged served run")
+    ap.add_argument("--dcache-chunk", type=int, default=65536, help="device-staged run: request pairs per chunk")
+    ap.add_argument("--dcache-keep", type=int, default=16,
+                    help="device-staged run: a pair not requested for this many chunks is released")
     ap.add_argument("--serve-check", type=int, default=24, help="pinned requests checked against the oracle")
     ap.add_argument("--summarize-rocprof", default=None, metavar="DIR")
     ap.add_argument("--summarize-traffic", nargs=2, default=None, metavar=("FETCH_DIR", "WRITE_DIR"))
