@@ -461,7 +461,7 @@ def measure_served(wl: Workload, args, dev):
     exact = exact and bool((wst == 0).all()) and bool(np.array_equal(np.concatenate(c_got), want))
     _log("%s: %d pinned requests (%d pairs) bit-exact vs oracle: %s" % (wl.name, len(check), len(c_ids), exact))
     staged = None if args.no_dcache else device_staged(P, dv, cache, cache_elems, wl.container, ids, lods, starts, nw,
-                                                        args.dcache_chunk, args.dcache_keep)
+                                                        args.dcache_chunk, args.dcache_keep, proc)
     del cache, dv
     torch.cuda.empty_cache()
 
@@ -498,7 +498,7 @@ def measure_served(wl: Workload, args, dev):
     return res
 
 
-def device_staged(P, dv, cache, cache_elems, container, ids, lods, starts, n_warm, chunk_pairs, keep=16):
+def device_staged(P, dv, cache, cache_elems, container, ids, lods, starts, n_warm, chunk_pairs, keep=16, proc=None):
     """The served trace with the cache stages on the device: whole requests
     concatenated into chunks of at most chunk_pairs pairs; per chunk one
     request/provision/assign call, one decode launch over the chunk's request
@@ -574,6 +574,11 @@ def device_staged(P, dv, cache, cache_elems, container, ids, lods, starts, n_war
     units = np.int64(1) << (3 * (5 - lods.astype(np.int64)))
     ok = bool((ts[new] == 0).all())
     full = int((st[m0:] == 3).sum())
+    if proc is not None:  # algorithmic bytes of every decode dispatch of this run (warm-up included)
+        recs = np.frombuffer(container, dtype=np.uint64, count=dv.info.n_bricks + 1, offset=int(dv.info.offsets_pos))
+        nid = ids[new].astype(np.int64)
+        proc["alg"] += float((recs[nid + 1] - recs[nid]).sum()) + 4.0 * float(units[new].sum())
+        proc["dispatches"] += sum(1 for ch in range(n_chunks) if pb[ch + 1] > pb[ch])
     # the last chunk's pairs against the oracle (a bounded sample)
     a = pb[-2]
     pick = np.arange(a, n)[:512]

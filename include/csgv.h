@@ -384,7 +384,8 @@ void csgv_server_destroy(csgv_server* server);
  *                 request of the same call).  CSGV_DC_JOINED: another request
  *                 of the same call provisions it.  CSGV_DC_FULL: absent, and
  *                 neither the free stack of its class nor the cache top had
- *                 room.  CSGV_DC_INVALID: no such brick, a LOD beyond its
+ *                 room (then every request of the pair is FULL).
+ *                 CSGV_DC_INVALID: no such brick, a LOD beyond its
  *                 side, or an unusable record.
  *   d_slot[i]     element offset of the pair's slot (NEW, HIT, JOINED), else
  *                 0xFFFFFFFFFFFFFFFF.
@@ -399,7 +400,9 @@ void csgv_server_destroy(csgv_server* server);
  *   requests of the same class (a full stack drops the slot until a reset).
  * csgv_dcache_reset empties the cache (all pairs absent, top 0, stacks empty).
  * csgv_dcache_query copies the top (elements) and the 7 stack counts to the
- *   host and synchronizes the stream.
+ *   host and synchronizes the stream.  The top only grows; a request that
+ *   does not fit leaves it past cache_elements, and from then on until a reset
+ *   only the free stacks provide slots (the paper resets a full cache).
  * Calls are stream-ordered: a request, decode and free issued on one stream
  * run in that order; calls on one cache from several streams at once race.
  * Errors: CSGV_EINVAL for null arguments (nothing enqueued), CSGV_EHIP when a

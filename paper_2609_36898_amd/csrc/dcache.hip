@@ -25,12 +25,18 @@
 // arrays as they are, with the request count the host already knows.
 //
 // Free-stack pops run only in the request kernel and pushes only in the free
-// kernel, so neither kernel sees both.  A pop decrements the count and owns
-// entry count-1 when the old count was positive; an unlucky pop adds its 1
-// back.  The first failing pop happens only once every entry is taken, and no
-// pop after it can succeed, so successful pops take distinct entries.  The top
-// works the same way: a failed advance is subtracted again, and while one is
-// outstanding the top exceeds the capacity, so no advance can succeed then.
+// kernel, so neither kernel sees both.  Both are aggregated per wavefront and
+// size class: one atomic per (wavefront, class) instead of one per request.
+// A pop of m entries subtracts m from the count and takes the min(m, old)
+// entries below the old count; the shortfall is added back.  The first short
+// pop happens only once every entry is taken, and since nothing is pushed
+// meanwhile no later pop sees a positive count, so the entries taken are
+// distinct.  Pushes mirror this against the stack's capacity.  The cache top
+// only grows: a wavefront adds the sum of its requests' slot sizes at once and
+// keeps the prefix of them that ends within the capacity.  Nothing is given
+// back, so ranges never overlap; a wavefront that overflows leaves the top
+// past the capacity, and from then on (until a reset) only the free stacks
+// provide slots -- the paper resets a cache that has filled up.
 #include <hip/hip_runtime.h>
 
 #include <string>
@@ -85,83 +91,137 @@ __global__ void dc_zero_counters_kernel(int* count, unsigned long long* top) {
     if (threadIdx.x == 0) *top = 0;
 }
 
+__device__ __forceinline__ uint64_t lanes_below(uint32_t lane) { return lane ? (~0ull >> (64 - lane)) : 0ull; }
+
 __global__ void __launch_bounds__(256) dc_request_kernel(DcState S, const uint32_t* ids, const uint8_t* lods,
                                                          uint32_t n, uint32_t* task_ids, uint64_t* slot,
                                                          uint32_t* state) {
-    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t id = ids[i], lod = lods[i];
-    task_ids[i] = kNoTask;
-    slot[i] = kEmpty;
-    const uint32_t L = id < S.n_bricks ? record_log2b(S, id) : 0xFFu;
-    if (L == 0xFFu || lod > L) {
-        state[i] = CSGV_DC_INVALID;
-        return;
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x, lane = __lane_id();
+    unsigned long long* key = nullptr;
+    uint32_t c = 0;
+    bool want = false;  // this request claimed an absent pair and provisions it
+    if (i < n) {
+        const uint32_t id = ids[i], lod = lods[i];
+        task_ids[i] = kNoTask;
+        slot[i] = kEmpty;
+        const uint32_t L = id < S.n_bricks ? record_log2b(S, id) : 0xFFu;
+        if (L == 0xFFu || lod > L) {
+            state[i] = CSGV_DC_INVALID;
+        } else {
+            key = S.slot_of + (uint64_t)id * 8 + lod;
+            const unsigned long long old = atomicCAS(key, kEmpty, kPending);
+            if (old == kPending) {  // another request of this launch provisions the pair
+                state[i] = CSGV_DC_JOINED;
+            } else if (old != kEmpty) {  // resident
+                slot[i] = old;
+                state[i] = CSGV_DC_HIT;
+            } else {
+                want = true;
+                c = L - lod;
+            }
+        }
     }
-    unsigned long long* key = S.slot_of + (uint64_t)id * 8 + lod;
-    const unsigned long long old = atomicCAS(key, kEmpty, kPending);
-    if (old == kPending) {  // another request of this launch provisions the pair
-        state[i] = CSGV_DC_JOINED;
-        return;
-    }
-    if (old != kEmpty) {  // resident
-        slot[i] = old;
-        state[i] = CSGV_DC_HIT;
-        return;
-    }
-    const uint32_t c = L - lod;
-    const unsigned long long units = 1ull << (3 * c);
+    // pops, one atomic per (wavefront, class); every lane runs this loop
     unsigned long long off = kEmpty;
-    const int k = atomicSub(&S.count[c], 1);
-    if (k > 0) {
-        off = S.stack[(uint64_t)c * S.stack_cap + (uint32_t)(k - 1)];
-    } else {
-        atomicAdd(&S.count[c], 1);
-        const unsigned long long t = atomicAdd(S.top, units);
-        if (t <= S.cache_elems && units <= S.cache_elems - t)
-            off = t;
-        else
-            atomicSub(S.top, units);
+    for (uint64_t left = __ballot(want); left;) {
+        const uint32_t lead = (uint32_t)__builtin_ctzll(left);
+        const uint32_t cc = (uint32_t)__shfl((int)c, (int)lead);
+        const bool mine = want && c == cc;
+        const uint64_t m = __ballot(mine);
+        const int cnt = __popcll(m);
+        int k = 0;
+        if (lane == lead) k = atomicSub(&S.count[cc], cnt);
+        k = __shfl(k, (int)lead);
+        const int avail = k > 0 ? min(k, cnt) : 0;
+        if (lane == lead && avail < cnt) atomicAdd(&S.count[cc], cnt - avail);
+        if (mine) {
+            const int rank = __popcll(m & lanes_below(lane));
+            if (rank < avail) off = S.stack[(uint64_t)cc * S.stack_cap + (uint32_t)(k - 1 - rank)];
+        }
+        left &= ~m;
     }
+    // the rest from the cache top: the wavefront's inclusive prefix of slot sizes
+    const bool need = want && off == kEmpty;
+    const unsigned long long units = need ? 1ull << (3 * c) : 0ull;
+    unsigned long long pre = units;
+    for (int d = 1; d < 64; d <<= 1) {
+        const unsigned long long v = __shfl_up(pre, (unsigned)d);
+        if (lane >= (uint32_t)d) pre += v;
+    }
+    const unsigned long long total = __shfl(pre, 63);
+    if (total) {
+        unsigned long long t = 0;
+        if (lane == 0) t = atomicAdd(S.top, total);
+        t = __shfl(t, 0);
+        const unsigned long long room = t < S.cache_elems ? S.cache_elems - t : 0ull;
+        if (need && pre <= room) off = t + pre - units;
+    }
+    if (!want) return;
     if (off == kEmpty) {
         atomicExch(key, kEmpty);
         state[i] = CSGV_DC_FULL;
         return;
     }
     atomicExch(key, off);
-    task_ids[i] = id;
+    task_ids[i] = ids[i];
     slot[i] = off;
     state[i] = CSGV_DC_NEW;
 }
 
-// joined requests take their winner's slot (or FULL when the winner found no room)
+// Joined requests take their winner's slot, or FULL when the winner found no
+// room.  A FULL request whose pair another request of the launch placed after
+// all (a later claim may fit where a wavefront's prefix did not) becomes a hit,
+// so after the call a pair is FULL in every request naming it or in none.
 __global__ void __launch_bounds__(256) dc_resolve_kernel(DcState S, const uint32_t* ids, const uint8_t* lods,
                                                          uint32_t n, uint64_t* slot, uint32_t* state) {
     const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n || state[i] != CSGV_DC_JOINED) return;
+    if (i >= n) return;
+    const uint32_t st = state[i];
+    if (st != CSGV_DC_JOINED && st != CSGV_DC_FULL) return;
     const unsigned long long v = S.slot_of[(uint64_t)ids[i] * 8 + lods[i]];
-    if (v == kEmpty || v == kPending)
-        state[i] = CSGV_DC_FULL;
-    else
+    if (v == kEmpty || v == kPending) {
+        if (st == CSGV_DC_JOINED) state[i] = CSGV_DC_FULL;
+    } else {
         slot[i] = v;
+        if (st == CSGV_DC_FULL) state[i] = CSGV_DC_HIT;
+    }
 }
 
 __global__ void __launch_bounds__(256) dc_free_kernel(DcState S, const uint32_t* ids, const uint8_t* lods,
                                                       uint32_t n) {
-    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t id = ids[i], lod = lods[i];
-    if (id >= S.n_bricks || lod > kMaxLog2b) return;
-    const unsigned long long old = atomicExch(S.slot_of + (uint64_t)id * 8 + lod, kEmpty);
-    if (old == kEmpty || old == kPending) return;
-    const uint32_t L = record_log2b(S, id);
-    if (L == 0xFFu || lod > L) return;  // cannot happen for a pair the request kernel placed
-    const uint32_t c = L - lod;
-    const int k = atomicAdd(&S.count[c], 1);
-    if ((uint32_t)k < S.stack_cap)
-        S.stack[(uint64_t)c * S.stack_cap + (uint32_t)k] = old;
-    else
-        atomicSub(&S.count[c], 1);  // stack full: the slot is not reused until a reset
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x, lane = __lane_id();
+    unsigned long long old = kEmpty;
+    uint32_t c = 0;
+    bool have = false;  // this request released a resident pair
+    if (i < n) {
+        const uint32_t id = ids[i], lod = lods[i];
+        if (id < S.n_bricks && lod <= kMaxLog2b) {
+            old = atomicExch(S.slot_of + (uint64_t)id * 8 + lod, kEmpty);
+            if (old != kEmpty && old != kPending) {
+                const uint32_t L = record_log2b(S, id);
+                have = L != 0xFFu && lod <= L;  // always so for a pair the request kernel placed
+                c = L - lod;
+            }
+        }
+    }
+    // pushes, one atomic per (wavefront, class); a full stack drops the slot until a reset
+    for (uint64_t left = __ballot(have); left;) {
+        const uint32_t lead = (uint32_t)__builtin_ctzll(left);
+        const uint32_t cc = (uint32_t)__shfl((int)c, (int)lead);
+        const bool mine = have && c == cc;
+        const uint64_t m = __ballot(mine);
+        const int cnt = __popcll(m);
+        int k = 0;
+        if (lane == lead) k = atomicAdd(&S.count[cc], cnt);
+        k = __shfl(k, (int)lead);
+        const int room = k < (int)S.stack_cap ? min((int)S.stack_cap - k, cnt) : 0;
+        if (lane == lead && room < cnt) atomicSub(&S.count[cc], cnt - room);
+        if (mine) {
+            const int rank = __popcll(m & lanes_below(lane));
+            if (rank < room) S.stack[(uint64_t)cc * S.stack_cap + (uint32_t)(k + rank)] = old;
+        }
+        left &= ~m;
+    }
 }
 
 }  // namespace

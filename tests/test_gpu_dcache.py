@@ -203,7 +203,7 @@ def test_request_decode_free_reuse_and_full(env):
         else:
             assert (b3.state[rows] == FULL).all()
     top, counts = dc.query()
-    assert top == cache_elems and np.array_equal(counts, left - placed3)
+    assert top >= cache_elems and np.array_equal(counts, left - placed3)
     res.update(got)
     _check_disjoint(res, cache_elems)
     _check_labels(c, cache, res)
@@ -216,5 +216,22 @@ def test_request_decode_free_reuse_and_full(env):
     b4 = Batch(P, dv, dc, plan, cache, cache_elems, ids, lods)
     assert (b4.state == NEW).all()
     _check_labels(c, cache, b4.placed())
+
+    # overfull batch on an empty cache: pairs of every size race for the top at once; the ones that get
+    # room must tile [0, top) with no overlap and no hole, the others are FULL
+    dc.reset()
+    k5 = _keys(rng, 400)
+    ids, lods = _requests(rng, k5, 2400)
+    b5 = Batch(P, dv, dc, plan, cache, cache_elems, ids, lods)
+    got = b5.placed()
+    assert 0 < len(got) < len(k5) and (b5.state == FULL).any()
+    full_pairs = set(zip(b5.ids[b5.state == FULL].tolist(), b5.lods[b5.state == FULL].tolist()))
+    assert not (full_pairs & set(got)), "a pair is FULL in one request and placed in another"
+    top, counts = dc.query()
+    assert top > cache_elems and (counts == 0).all()
+    # the placed slots tile [0, their total) with no hole and no overlap
+    _check_disjoint(got, cache_elems)
+    assert max(s + _units(l) for (i, l), s in got.items()) == sum(_units(l) for _, l in got) <= cache_elems
+    _check_labels(c, cache, got)
     dc.destroy()
-    _say("dcache: 3 batches, reuse and full cache checked")
+    _say("dcache: 5 batches, reuse, full and overfull cache checked")
