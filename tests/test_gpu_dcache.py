@@ -235,3 +235,80 @@ def test_request_decode_free_reuse_and_full(env):
     _check_labels(c, cache, got)
     dc.destroy()
     _say("dcache: 5 batches, reuse, full and overfull cache checked")
+
+
+def test_mixed_brick_sides_use_size_classes():
+    """32^3 and 64^3 bricks (u64 labels): a slot's size class is log2(side) - LOD, so a freed 64^3 LOD-1
+    slot (32^3 elements) serves a 32^3 LOD-0 pair and never a 64^3 LOD-0 one."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2609_36898_amd as P
+    n_b = 12
+    l2 = np.array([6 if i % 2 == 0 else 5 for i in range(n_b)], np.uint8)
+    bricks = [synth.uneven_brick_u64(1 << int(l2[i]), 23, i)[0].reshape(-1) for i in range(n_b)]
+    c = oracle.encode_bricks(np.concatenate(bricks), l2, 8)
+    dv = P.DeviceVolume(c)
+    side = lambda i: int(l2[i])  # noqa: E731
+    units = lambda i, l: 1 << (3 * (side(i) - int(l)))  # noqa: E731
+    cache_elems = 3 * 64 ** 3
+    cache = torch.zeros(cache_elems, dtype=torch.int64, device="cuda")
+    dc = P.csgv.csgv_dcache(dv.info, dv.tensor, cache_elems, stack_cap=64)
+    plan = P.csgv_plan(dv.info, 256)
+
+    def batch(pairs):
+        ids = np.array([p[0] for p in pairs], np.uint32)
+        lods = np.array([p[1] for p in pairs], np.uint8)
+        n = len(pairs)
+        d_ids = torch.from_numpy(ids.view(np.int32).copy()).cuda()
+        d_lods = torch.from_numpy(lods.copy()).cuda()
+        task = torch.empty(n, dtype=torch.int32, device="cuda")
+        slot = torch.empty(n, dtype=torch.int64, device="cuda")
+        state = torch.empty(n, dtype=torch.int32, device="cuda")
+        status = torch.empty(n, dtype=torch.int32, device="cuda")
+        _say("mixed sides: request + decode of", n, "requests")
+        dc.request(None, d_ids, d_lods, n, task, slot, state)
+        plan.launch(None, dv.tensor, task, d_lods, slot, n, cache, cache_elems, status)
+        torch.cuda.synchronize()
+        st = state.cpu().numpy()
+        sl = slot.cpu().numpy().view(np.uint64)
+        ts = status.cpu().numpy()
+        assert (ts[st == NEW] == 0).all()
+        return st, sl
+
+    def labels_ok(pairs, slots):
+        ids = np.array([p[0] for p in pairs], np.uint32)
+        lods = np.array([p[1] for p in pairs], np.uint8)
+        offs, total = P.dense_offsets(l2[ids.astype(np.int64)], lods)
+        want, wst = oracle.decode_tasks(c, ids, lods, offs, total, 8, nthreads=8)
+        host = cache.cpu().numpy().view(np.uint64)
+        assert (wst == 0).all()
+        for (i, l), s, o in zip(pairs, slots, offs):
+            u = units(i, l)
+            assert np.array_equal(host[int(s):int(s) + u], want[int(o):int(o) + u]), "pair %d/%d" % (i, l)
+
+    # a 64^3 brick at LOD 0 and LOD 1, a 32^3 brick at LOD 0 and LOD 1
+    first = [(0, 0), (0, 1), (1, 0), (1, 1)]
+    st, sl1 = batch(first)
+    assert (st == NEW).all()
+    assert dc.query()[0] == 64 ** 3 + 2 * 32 ** 3 + 16 ** 3
+    labels_ok(first, sl1)
+    # release the 64^3 LOD-1 slot (class 5, 32^3 elements) and the 32^3 LOD-1 slot (class 4)
+    fids = torch.from_numpy(np.array([0, 1], np.int32)).cuda()
+    flods = torch.from_numpy(np.array([1, 1], np.uint8)).cuda()
+    dc.free(None, fids, flods, 2)
+    top, counts = dc.query()
+    assert counts[5] == 1 and counts[4] == 1 and counts.sum() == 2
+    # class 5 (32^3 elements): a 32^3 brick at LOD 0 and a 64^3 brick at LOD 1 -- one pops the freed
+    # 64^3 LOD-1 slot, the other takes the top; class 4: a 64^3 brick at LOD 2 pops the freed 32^3 LOD-1 slot
+    second = [(3, 0), (2, 1), (4, 2)]
+    st, sl = batch(second)
+    assert (st == NEW).all()
+    top2, counts2 = dc.query()
+    assert (counts2 == 0).all() and top2 == top + 32 ** 3
+    assert sorted(int(v) for v in sl[:2]) == sorted([int(sl1[1]), top])
+    assert int(sl[2]) == int(sl1[3])
+    keep = [first[0], first[2]] + second
+    labels_ok(keep, [sl1[0], sl1[2]] + list(sl))
+    dc.destroy()
+    _say("dcache: mixed brick sides checked")
