@@ -549,6 +549,7 @@ def device_staged(P, dv, cache, cache_elems, container, ids, lods, starts, n_war
     stream = torch.cuda.current_stream(dev)
     dc = P.csgv.csgv_dcache(dv.info, dv.tensor, cache_elems, stream=stream)
     plan = P.csgv_plan(dv.info, max(int(np.diff(pb).max()), 1))
+    plan.set_graph(False)  # every chunk has its own arrays and count: a captured graph would be rebuilt each time
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.time()
@@ -563,8 +564,8 @@ def device_staged(P, dv, cache, cache_elems, container, ids, lods, starts, n_war
         if r1 > r0:
             dc.free(stream, d_rel_ids[r0:], d_rel_lods[r0:], r1 - r0)
     ev1.record(stream)
+    host_s = time.time() - t0  # enqueueing every chunk, warm-up included (the device may still be busy)
     torch.cuda.synchronize()
-    host_s = time.time() - t0
     secs = ev0.elapsed_time(ev1) * 1e-3
     st = state.cpu().numpy()
     ts = status.cpu().numpy()
