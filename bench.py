@@ -498,6 +498,38 @@ def measure_served(wl: Workload, args, dev):
     return res
 
 
+def chunk_schedule(ids, lods, starts, n_warm, chunk_pairs, keep):
+    """Chunks of whole requests (at most chunk_pairs pairs unless one request is larger; the first
+    measured request starts a chunk) and the release schedule: a pair used in chunk c and not again
+    in chunks c+1..c+keep is released right after chunk c+keep (pairs still in use at the end stay).
+    Returns the chunks' pair boundaries, the first measured chunk, the released keys (id * 8 + lod)
+    ordered by chunk, and per chunk the range of its releases in that list."""
+    n_req = len(starts) - 1
+    sizes = np.diff(starts.astype(np.int64))
+    bounds, acc = [0], 0
+    for r in range(n_req):
+        if (acc + sizes[r] > chunk_pairs and acc > 0) or (r == n_warm and r > 0):
+            bounds.append(r)
+            acc = 0
+        acc += int(sizes[r])
+    bounds.append(n_req)
+    pb = [int(starts[b]) for b in bounds]
+    n_chunks = len(bounds) - 1
+    first_measured = bounds.index(n_warm) if n_warm < n_req else n_chunks
+    chunk_of = np.repeat(np.arange(n_chunks), np.diff(pb))
+    key = ids.astype(np.int64) * 8 + lods.astype(np.int64)
+    kc = np.unique(key * n_chunks + chunk_of)
+    k, c = kc // n_chunks, kc % n_chunks
+    nxt = np.full(len(kc), 1 << 40, np.int64)
+    same = k[1:] == k[:-1]
+    nxt[:-1][same] = c[1:][same]
+    rel = (nxt - c > keep) & (c + keep < n_chunks)
+    rk, rat = k[rel], c[rel] + keep
+    order = np.argsort(rat, kind="stable")
+    rk, rat = rk[order], rat[order]
+    return pb, first_measured, rk, np.searchsorted(rat, np.arange(n_chunks + 1))
+
+
 def device_staged(P, dv, cache, cache_elems, container, ids, lods, starts, n_warm, chunk_pairs, keep=16, proc=None):
     """The served trace with the cache stages on the device: whole requests
     concatenated into chunks of at most chunk_pairs pairs; per chunk one
@@ -512,30 +544,8 @@ def device_staged(P, dv, cache, cache_elems, container, ids, lods, starts, n_war
     import oracle
     dev = cache.device
     n_req = len(starts) - 1
-    sizes = np.diff(starts.astype(np.int64))
-    bounds, acc = [0], 0
-    for r in range(n_req):
-        if (acc + sizes[r] > chunk_pairs and acc > 0) or r == n_warm:
-            bounds.append(r)
-            acc = 0
-        acc += int(sizes[r])
-    bounds.append(n_req)
-    pb = [int(starts[b]) for b in bounds]  # pair boundaries of the chunks
-    n_chunks = len(bounds) - 1
-    first_measured = bounds.index(n_warm)
-    # release schedule: a pair used in chunk c and not again within `keep` chunks is freed after chunk c + keep
-    chunk_of = np.repeat(np.arange(n_chunks), np.diff(pb))
-    key = ids.astype(np.int64) * 8 + lods.astype(np.int64)
-    kc = np.unique(key * n_chunks + chunk_of)
-    k, c = kc // n_chunks, kc % n_chunks
-    nxt = np.full(len(kc), 1 << 40, np.int64)
-    same = k[1:] == k[:-1]
-    nxt[:-1][same] = c[1:][same]
-    rel = (nxt - c > keep) & (c + keep < n_chunks)
-    rk, rat = k[rel], c[rel] + keep
-    order = np.argsort(rat, kind="stable")
-    rk, rat = rk[order], rat[order]
-    rel_b = np.searchsorted(rat, np.arange(n_chunks + 1))
+    pb, first_measured, rk, rel_b = chunk_schedule(ids, lods, starts, n_warm, chunk_pairs, keep)
+    n_chunks = len(pb) - 1
     d_rel_ids = torch.from_numpy((rk // 8).astype(np.uint32).view(np.int32)).to(dev)
     d_rel_lods = torch.from_numpy((rk % 8).astype(np.uint8)).to(dev)
 
