@@ -532,8 +532,8 @@ def chunk_schedule(ids, lods, starts, n_warm, chunk_pairs, keep):
 
 def device_staged(P, dv, cache, cache_elems, container, ids, lods, starts, n_warm, chunk_pairs, keep=16, proc=None):
     """The served trace with the cache stages on the device: whole requests
-    concatenated into chunks of at most chunk_pairs pairs; per chunk one
-    request/provision/assign call, one decode launch over the chunk's request
+    concatenated into chunks of at most chunk_pairs pairs, each distinct pair
+    of a chunk requested once; per chunk one request/provision/assign call, one decode launch over the chunk's request
     arrays (non-tasks are rejected by the decoder), then the release of every
     pair whose last use was `keep` chunks ago (the no-longer-requested pairs go
     onto the free stacks).  Every chunk is enqueued on one stream up front: no
@@ -549,9 +549,18 @@ def device_staged(P, dv, cache, cache_elems, container, ids, lods, starts, n_war
     d_rel_ids = torch.from_numpy((rk // 8).astype(np.uint32).view(np.int32)).to(dev)
     d_rel_lods = torch.from_numpy((rk % 8).astype(np.uint8)).to(dev)
 
-    n = int(starts[-1])
-    d_ids = torch.from_numpy(ids.astype(np.uint32).view(np.int32)).to(dev)
-    d_lods = torch.from_numpy(lods.astype(np.uint8)).to(dev)
+    # a chunk's request list names each pair once, as the paper's request stage does per frame
+    served = float((np.int64(1) << (3 * (5 - lods[pb[first_measured]:].astype(np.int64)))).sum())
+    req_pairs = int(starts[-1]) - int(starts[n_warm])
+    chunk_of = np.repeat(np.arange(n_chunks, dtype=np.int64), np.diff(pb))
+    uk = np.unique((chunk_of << 40) + ids.astype(np.int64) * 8 + lods.astype(np.int64))
+    ub = [int(v) for v in np.searchsorted(uk >> 40, np.arange(n_chunks + 1))]
+    ids = ((uk & ((1 << 40) - 1)) // 8).astype(np.uint32)
+    lods = ((uk & ((1 << 40) - 1)) % 8).astype(np.uint8)
+    pb = ub
+    n = len(uk)
+    d_ids = torch.from_numpy(ids.view(np.int32)).to(dev)
+    d_lods = torch.from_numpy(lods).to(dev)
     task = torch.empty(n, dtype=torch.int32, device=dev)
     slot = torch.empty(n, dtype=torch.int64, device=dev)
     state = torch.empty(n, dtype=torch.int32, device=dev)
@@ -605,8 +614,9 @@ def device_staged(P, dv, cache, cache_elems, container, ids, lods, starts, n_war
     res = {"requests": n_meas, "chunks": n_chunks - first_measured, "max_chunk_pairs": chunk_pairs,
            "release_after_chunks": keep, "seconds": round(secs, 4), "requests_per_s": round(n_meas / secs, 2),
            "decoded_gvoxel_s": round(float(units[m0:][new[m0:]].sum()) / secs / 1e9, 3),
-           "served_gvoxel_s": round(float(units[m0:].sum()) / secs / 1e9, 3),
-           "hit_fraction": round(float((~new[m0:]).sum() - full) / max(n - m0, 1), 4),
+           "served_gvoxel_s": round(served / secs / 1e9, 3),
+           "chunk_pairs": n - m0,
+           "hit_fraction": round(1.0 - float(new[m0:].sum() + full) / max(req_pairs, 1), 4),
            "full_pairs": full, "cache_top_elements": top, "host_enqueue_s": round(host_s, 3),
            "checked_pairs": int(len(pids)), "bit_exact": exact}
     _log("device-staged: %.0f req/s, %.2f GVoxel/s decoded, %d chunks, hit fraction %.3f, full %d, exact %s" % (
