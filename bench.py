@@ -166,6 +166,7 @@ def build_workload(name: str) -> Workload:
     else:
         raise ValueError("unknown workload " + name)
     wl.config["compressed_bytes"] = len(c)
+    wl.config["container_sha256_16"] = hashlib.sha256(c).hexdigest()[:16]  # identifies the synthetic input
     wl.config["label_bytes"] = wl.label_bytes
     _log("%s: built in %.1f s, %d tasks, %d compressed bytes" % (name, time.time() - t0, len(wl.ids), len(c)))
     return wl
