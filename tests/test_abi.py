@@ -187,3 +187,10 @@ def test_dcache_rejects_null_arguments_synchronously(P):
                P.csgv._lib.csgv_dcache_query(None, None, None, None)):
         assert rc == P.csgv.CSGV_EINVAL
     assert b"null" in P.csgv._lib.csgv_dcache_last_error()
+
+
+def test_dcache_state_codes_match_header(P):
+    src = open(os.path.join(ROOT, "include", "csgv.h")).read()
+    codes = dict((k, int(v)) for k, v in re.findall(r"\bCSGV_DC_([A-Z]+)\s*=\s*(\d+)", src))
+    assert codes == {"NEW": P.csgv.DC_NEW, "HIT": P.csgv.DC_HIT, "JOINED": P.csgv.DC_JOINED,
+                     "FULL": P.csgv.DC_FULL, "INVALID": P.csgv.DC_INVALID}
