@@ -39,6 +39,7 @@
 // provide slots -- the paper resets a cache that has filled up.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <string>
 
 #include "csgv.h"
